@@ -1,0 +1,105 @@
+"""Orientation matching: distances, argmin, top-2 gap, error bounds, BF16.
+
+Section II-B: each of the N experimental images is compared with all M model
+images and takes the orientation of the closest one in Euclidean distance
+(O(MN) work).  Readings: D[m, n] = sum_p (s_mp - d_np)^2; ties go to the
+lowest model index m (first occurrence).
+
+The GPU computes D as |s|^2 + |d|^2 - 2 s.d in FP32 (and optionally with BF16
+products); the bounds here state how far such a value can sit from the
+exact one, so that tests can demand identical argmins exactly where the
+exact top-2 gap exceeds them.
+
+TEST INFRASTRUCTURE ONLY (see package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+U32 = 2.0 ** -24   # unit roundoff of IEEE binary32
+UBF = 2.0 ** -8    # unit roundoff of bfloat16 (8-bit significand)
+
+
+def distances_direct(S, D) -> np.ndarray:
+    """D[m, n] = sum_p (S[m,p] - D[n,p])^2 summed directly, FP64 (tiny)."""
+    S = np.asarray(S, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    out = np.empty((S.shape[0], D.shape[0]))
+    for n in range(D.shape[0]):
+        diff = S - D[n][None, :]
+        out[:, n] = (diff * diff).sum(axis=1)
+    return out
+
+
+def distances_expanded(S, D) -> np.ndarray:
+    """|s_m|^2 + |d_n|^2 - 2 s_m.d_n in FP64 (same value as the direct sum
+    up to FP64 rounding)."""
+    S = np.asarray(S, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    sn = (S * S).sum(axis=1)
+    dn = (D * D).sum(axis=1)
+    return sn[:, None] + dn[None, :] - 2.0 * (S @ D.T)
+
+
+def argmin_first(Dmat) -> np.ndarray:
+    """Per image (column), the lowest m attaining the minimum distance."""
+    return np.argmin(np.asarray(Dmat), axis=0).astype(np.int64)
+
+
+def top2(Dmat):
+    """Per column: (smallest value, second smallest value)."""
+    part = np.partition(np.asarray(Dmat), 1, axis=0)
+    return part[0], part[1]
+
+
+def gamma(L: int, u: float = U32) -> float:
+    """gamma_L = L u / (1 - L u): the standard bound on the relative error
+    of L chained floating-point additions/multiplications."""
+    return L * u / (1.0 - L * u)
+
+
+def fp32_distance_bound(snorm2, dnorm2, absdot, L: int) -> np.ndarray:
+    """Bound on |fl32(D) - D| for D = |s|^2 + |d|^2 - 2 s.d evaluated in
+    FP32 when every sum in it is a chain of at most L roundings:
+    gamma_L (|s|^2 + |d|^2 + 2 sum_p |s_p d_p|)."""
+    return gamma(L) * (np.asarray(snorm2) + np.asarray(dnorm2) + 2.0 * np.asarray(absdot))
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even) and
+    return them as float32."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32)
+
+
+def bf16_proxy_bound(absdot, e_fp32, exact_images: bool) -> np.ndarray:
+    """Bound on |b - D| for the BF16 proxy b = |s|^2 + |d|^2 - 2 (s~.d~)
+    with s~, d~ rounded to BF16 and FP32 norms.  Each product moves by at
+    most (2u + u^2)|s_p d_p| (u only, if every image value is exact in BF16),
+    so |b - D| <= 2 (2u + u^2) sum|s_p d_p| + e_fp32."""
+    rel = UBF if exact_images else (2.0 * UBF + UBF * UBF)
+    return 2.0 * rel * np.asarray(absdot) + np.asarray(e_fp32)
+
+
+def topk(Dmat, k: int):
+    """Per column, the k smallest values' row indices, ordered by (value,
+    index); shape (k, n_cols)."""
+    Dm = np.asarray(Dmat)
+    order = np.lexsort((np.broadcast_to(np.arange(Dm.shape[0])[:, None], Dm.shape), Dm), axis=0)
+    return order[:k]
+
+
+def topk_certified(b, ebf, k: int = 8) -> np.ndarray:
+    """Per column, whether the k smallest BF16 proxies b provably contain the
+    exact argmin: b_(k+1) - b_(1) > E_(1) + max_m E_m, where E is the proxy
+    error bound (the exact minimiser m* has b_{m*} <= b_(1) + E_(1) + E_{m*})."""
+    b = np.asarray(b)
+    ebf = np.asarray(ebf)
+    order = np.argsort(b, axis=0, kind="stable")
+    cols = np.arange(b.shape[1])
+    b1 = b[order[0], cols]
+    bk1 = b[order[k], cols]
+    e1 = ebf[order[0], cols]
+    return (bk1 - b1) > (e1 + ebf.max(axis=0))
