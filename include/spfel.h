@@ -1,0 +1,173 @@
+/*
+ * spfel.h - C ABI of the MI355X slice-and-match library.
+ *
+ * The operations are those of the Cartesian-NUFFT M-TIP reconstruction of
+ * SpiniFEL (arXiv 2109.05339):
+ *   - slicing (section II-A): M model images on a fixed set of orientations,
+ *     the type-2 (uniform -> nonuniform) NUFFT of the model coefficients at
+ *     the detector's Ewald-sphere points rotated by each orientation;
+ *   - orientation matching (section II-B): every experimental image against
+ *     every model image in Euclidean distance, O(MN), nearest model wins;
+ *   - merging (section II-C, Eq. (1)-(2)): the type-1 NUFFT A* of the
+ *     (weighted) oriented data, the right-hand side A* D b of Eq. (2) and the
+ *     adjoint of slicing.
+ *
+ * Conventions shared by every call
+ *   Model: N odd, h = (N-1)/2, array model[i0][i1][i2] (C order, i2 fastest)
+ *     holds mode k = (i0-h, i1-h, i2-h).  REAL domain: float32 coefficients,
+ *     slice value s(x) = sum_k m_k cos(k.x).  COMPLEX domain: interleaved
+ *     complex64 (re, im), s(x) = sum_k m_k exp(+i k.x).
+ *   Points: x = R(q) q_p in radians per voxel; R(q) is the rotation of the
+ *     unit quaternion q = (w, x, y, z) (Hamilton convention; the library
+ *     renormalises, so q and -q give the same slice).  det_q is P x 3 float32.
+ *     s is 2 pi periodic in each coordinate of x.
+ *   NUFFT: exponential-of-semicircle kernel psi(tau) = exp(beta(sqrt(1 -
+ *     (2 tau / w)^2) - 1)) of width w cells, beta = beta_over_w * w,
+ *     fine grid n_f = 2N per axis, support cells t - w/2 <= l < t + w/2 with
+ *     t = x n_f / (2 pi).
+ *   Memory: every pointer argument is a device pointer on the plan's device
+ *     (or on the current device for plan-less calls), owned by the caller,
+ *     4-byte aligned (8-byte for complex64, 16-byte preferred).
+ *   Streams: `stream` is a hipStream_t (NULL = default stream).  Every call
+ *     only enqueues work on it and returns; nothing synchronises the device.
+ *   Errors: every call returns an spfel_status; on failure nothing has been
+ *     enqueued (validation runs before any launch) unless the status is
+ *     SPFEL_EHIP, and spfel_last_error() describes the failure.  No C++
+ *     exception crosses this boundary; a plan stays usable after any error.
+ */
+#ifndef SPFEL_H
+#define SPFEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spfel_plan_s *spfel_plan;
+
+typedef enum {
+  SPFEL_OK = 0,
+  SPFEL_EINVAL = -1,        /* invalid argument (null, size, alignment) */
+  SPFEL_ERANGE = -2,        /* size beyond what the library supports */
+  SPFEL_ENOMEM = -3,        /* device allocation failed */
+  SPFEL_EHIP = -4,          /* a HIP call or kernel launch failed */
+  SPFEL_ESTATE = -5,        /* destroyed plan, or model not set */
+  SPFEL_EUNSUPPORTED = -6   /* valid but unsupported parameter combination */
+} spfel_status;
+
+enum { SPFEL_REAL = 0, SPFEL_COMPLEX = 1 };
+enum { SPFEL_F32 = 0, SPFEL_BF16 = 1 };
+enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1 };
+enum { SPFEL_MERGE_ACCUMULATE = 1, SPFEL_MERGE_DEFER = 2 };
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int spfel_version(void);
+
+/* Description of the last failure on the calling thread ("" if none).
+ * Valid until the next spfel call on that thread. */
+const char *spfel_last_error(void);
+
+/* Create a plan for model size n_model (odd, >= 3) on HIP device `device`.
+ * kernel_width w in 4..8 and w <= n_model; upsampfac must be 2.0 (fine grid
+ * n_f = 2N); beta_over_w in (0, 10] (2.30 is the usual value at upsampling
+ * 2); domain SPFEL_REAL or SPFEL_COMPLEX.  All device memory the plan needs
+ * (fine grid, transform tables, spreading accumulator, intermediates) is
+ * allocated here; later calls allocate nothing.  *out receives the handle. */
+int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
+                      double upsampfac, double beta_over_w, int domain,
+                      int device);
+
+/* Release a plan and its device memory.  Work still queued on a stream that
+ * uses the plan must have completed.  A destroyed handle is rejected with
+ * SPFEL_ESTATE by every later call. */
+int spfel_plan_destroy(spfel_plan plan);
+
+/* Plan facts: fine-grid size per axis and device bytes held (either pointer
+ * may be NULL). */
+int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes);
+
+/* Section II-A, the model-side half of the type-2 NUFFT: deconvolve the
+ * model by the kernel's Fourier transform, zero-pad to n_f^3 and transform
+ * to the oversampled grid the interpolation reads.  `model` is N^3 float32
+ * (REAL) or complex64 (COMPLEX).  The plan keeps the grid until the next
+ * set_model; `model` may be reused as soon as the stream reaches this call. */
+int spfel_set_model(spfel_plan plan, const void *model, void *stream);
+
+/* Section II-A: slice the model at M orientations.  quats: M x 4 float32;
+ * det_q: P x 3 float32.  Outputs (each may be NULL, not all):
+ *   out       M x P row-major, float32 (REAL) or complex64 (COMPLEX);
+ *   out_bf16  M x P bfloat16 (round to nearest even) copy, REAL only;
+ *   out_norm2 M float32 squared norms |s_m|^2 (sum of |s|^2 over P).
+ * Requires spfel_set_model.  M = 0 or P = 0 is valid (norms become 0). */
+int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
+                const float *det_q, int64_t P, void *out, uint16_t *out_bf16,
+                float *out_norm2, void *stream);
+
+/* Squared row norms of a rows x cols matrix, float32 (dtype SPFEL_F32) or
+ * bfloat16 values (SPFEL_BF16), accumulated in float32 in a fixed order
+ * (each row: 256 strided partial sums, then a pairwise tree). */
+int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
+                    float *out, void *stream);
+
+/* Bytes of device workspace spfel_match needs for these sizes and mode. */
+size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P,
+                                   int mode);
+
+/* Section II-B: for each image n, the model image m minimising
+ *   D[m, n] = |s_m|^2 + |d_n|^2 - 2 s_m . d_n
+ * (float32 arithmetic, lowest m on ties), merged into the caller's running
+ * best: best_idx/best_dist (n_img each) are read and updated, so chunks of
+ * model images can be streamed with m_offset = index of the chunk's first
+ * model image.  Initialise best_idx = -1 and best_dist = +inf.
+ *   mode SPFEL_MATCH_FP32: slices/images float32 M x P / n_img x P.  Each
+ *     distance is a chain of at most 36 + ceil(P/32) float32 roundings.
+ *   mode SPFEL_MATCH_BF16_RESCORE8: slices/images bfloat16; the products
+ *     run in bfloat16 with float32 accumulation, each image keeps the 8
+ *     smallest proxy distances, and those 8 are rescored exactly as above
+ *     from slices_f32/images_f32 (required, float32).  The rescored
+ *     distance is a chain of at most 10 + ceil(P/64) roundings.
+ * slice_norm2/image_norm2: float32 squared norms (spfel_row_norm2 of the
+ * float32 data).  workspace: at least spfel_match_workspace_bytes bytes. */
+int spfel_match(const void *slices, const float *slice_norm2,
+                const void *images, const float *image_norm2, int64_t M,
+                int64_t n_img, int64_t P, int64_t m_offset, int mode,
+                const float *slices_f32, const float *images_f32,
+                int32_t *best_idx, float *best_dist, void *workspace,
+                size_t workspace_bytes, void *stream);
+
+/* Section II-C, Eq. (2) right-hand side: the type-1 NUFFT (adjoint of
+ * slicing) of values at the points R(quats[n]) det_q[p]:
+ *   REAL:    out_k = sum_{n,p} y_np cos(k . x_np)
+ *   COMPLEX: out_k = sum_{n,p} y_np exp(-i k . x_np)
+ * with y = values (n_img x P, float32 or complex64) times weights (n_img x P
+ * float32, or NULL for 1).  out is N^3 float32 / complex64.  flags:
+ *   SPFEL_MERGE_ACCUMULATE  out += result instead of out = result;
+ *   SPFEL_MERGE_DEFER       only spread into the plan's accumulator; the
+ *                           next call without DEFER finishes the sum of all
+ *                           deferred calls and writes out (out may be NULL
+ *                           with DEFER).
+ * Spreading uses float32 atomics, so the summation order (and the last bits
+ * of the result) can vary between runs. */
+int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
+                        const float *det_q, int64_t P, const void *values,
+                        const float *weights, void *out, int flags,
+                        void *stream);
+
+/* Weighted residual of slices against images (the gradient's spread input
+ * for the weighted loss of Eq. (2)'s D-weighted least squares):
+ *   residual[i] = scale * w_i * (s_i - d_i)        (may be NULL)
+ *   *loss += sum_i w_i |s_i - d_i|^2               (float64, may be NULL)
+ * over `count` elements (float32 or complex64 per the plan's domain;
+ * weights NULL means 1).  The loss sum has a fixed order. */
+int spfel_weighted_residual(spfel_plan plan, const void *slices,
+                            const void *images, const float *weights,
+                            int64_t count, float scale, void *residual,
+                            double *loss, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPFEL_H */

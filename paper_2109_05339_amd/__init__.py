@@ -1,0 +1,13 @@
+"""MI355X-native slice-and-match for single-particle imaging (arXiv
+2109.05339): type-2 NUFFT slicing, Euclidean orientation matching (FP32 or
+BF16 with FP32 rescoring) and the type-1 adjoint spread, as hand-written
+gfx950 kernels behind the C ABI of include/spfel.h.
+"""
+from ._lib import (SpfelError, SpfelInvalidArgument, SpfelStateError,  # noqa: F401
+                   SpfelUnsupported, SpfelOutOfMemory, LIB_PATH, lib)
+from .ops import (Plan, row_norm2, match, match_workspace_bytes, new_best,  # noqa: F401
+                  REAL, COMPLEX, MATCH_FP32, MATCH_BF16_RESCORE8, MERGE_ACCUMULATE,
+                  MERGE_DEFER)
+from .autograd import SliceFn, SliceLossFn, slice_model, slice_loss  # noqa: F401
+
+lib()  # fail loudly at import if the library is not built

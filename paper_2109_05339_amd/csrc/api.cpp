@@ -1,0 +1,452 @@
+// libspfel C ABI: argument validation, plan lifecycle and dispatch to the
+// kernel launchers.  No exception crosses this file's extern "C" functions.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace spfel {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SPFEL_EHIP;
+}
+void clear_error() { g_err.clear(); }
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on the
+// three-term recurrence of the Legendre polynomials.
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &wt) {
+  x.resize(n);
+  wt.resize(n);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    wt[i] = wt[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// psi_hat(k) = int_{-w/2}^{w/2} psi(tau) cos(2 pi k tau / nf) dtau.  With
+// tau = (w/2) sin(theta) the integrand exp(beta (cos theta - 1))
+// cos(pi k w sin(theta) / nf) (w/2) cos(theta) is smooth on [-pi/2, pi/2],
+// so Gauss-Legendre in theta converges geometrically.
+void kernel_transform(int N, int nf, int w, double beta, double *out) {
+  std::vector<double> z, wt;
+  const int n = 160;
+  gauss_legendre(n, z, wt);
+  const int h = (N - 1) / 2;
+  for (int k = -h; k <= h; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double th = 0.5 * M_PI * z[i];
+      double tau = 0.5 * w * std::sin(th);
+      double g = std::exp(beta * (std::cos(th) - 1.0)) *
+                 std::cos(2.0 * M_PI * k * tau / nf) * 0.5 * w * std::cos(th);
+      s += wt[i] * g;
+    }
+    out[k + h] = 0.5 * M_PI * s;
+  }
+}
+
+static std::mutex g_mu;
+static std::set<Plan *> g_live;
+
+static bool live(Plan *p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return p != nullptr && g_live.count(p) != 0;
+}
+
+// Switches to a device for the scope of a call and back.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+static bool aligned(const void *p, size_t a) {
+  return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+static void free_plan(Plan *p) {
+  void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+}
+
+static bool test_fail_alloc() {
+  const char *e = std::getenv("SPFEL_TEST_FAIL_ALLOC");
+  return e != nullptr && e[0] == '1';
+}
+
+}  // namespace spfel
+
+using namespace spfel;
+
+extern "C" {
+
+int spfel_version(void) { return 100; }
+
+const char *spfel_last_error(void) { return g_err.c_str(); }
+
+int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
+                      double upsampfac, double beta_over_w, int domain,
+                      int device) {
+  clear_error();
+  if (!out) return fail(SPFEL_EINVAL, "plan_create: out is NULL");
+  *out = nullptr;
+  if (n_model < 3 || n_model % 2 == 0)
+    return fail(SPFEL_EINVAL, "plan_create: n_model must be odd and >= 3");
+  if (n_model > 511) return fail(SPFEL_ERANGE, "plan_create: n_model > 511");
+  if (kernel_width < 2 || kernel_width > 16)
+    return fail(SPFEL_EINVAL, "plan_create: kernel_width out of [2, 16]");
+  if (kernel_width > n_model)
+    return fail(SPFEL_EINVAL, "plan_create: kernel_width > n_model");
+  if (kernel_width < 4 || kernel_width > 8)
+    return fail(SPFEL_EUNSUPPORTED, "plan_create: kernel_width must be 4..8");
+  if (!(upsampfac == 2.0))
+    return fail(SPFEL_EUNSUPPORTED, "plan_create: only upsampfac 2.0 (n_f = 2N)");
+  if (!(beta_over_w > 0.0 && beta_over_w <= 10.0))
+    return fail(SPFEL_EINVAL, "plan_create: beta_over_w out of (0, 10]");
+  if (domain != SPFEL_REAL && domain != SPFEL_COMPLEX)
+    return fail(SPFEL_EINVAL, "plan_create: domain must be REAL or COMPLEX");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "plan_create: hipGetDeviceCount");
+  if (device < 0 || device >= ndev)
+    return fail(SPFEL_EINVAL, "plan_create: no such device");
+  DeviceGuard g(device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "plan_create: hipSetDevice");
+
+  Plan *p = new (std::nothrow) Plan();
+  if (!p) return fail(SPFEL_ENOMEM, "plan_create: host allocation");
+  p->device = device;
+  p->N = n_model;
+  p->nf = 2 * n_model;
+  p->w = kernel_width;
+  p->domain = domain;
+  p->beta = beta_over_w * kernel_width;
+  const size_t N = n_model, nf = p->nf;
+  const size_t el = domain == SPFEL_COMPLEX ? sizeof(float2) : sizeof(float);
+  const size_t grid_b = nf * nf * nf * el;
+  const size_t tab_b = N * nf * sizeof(float2);
+  const size_t tmp_b = 4 * N * N * N * sizeof(float2);
+  struct Req {
+    void **ptr;
+    size_t bytes;
+  } reqs[] = {{&p->u, grid_b},
+              {reinterpret_cast<void **>(&p->wpos), tab_b},
+              {reinterpret_cast<void **>(&p->wneg), tab_b},
+              {reinterpret_cast<void **>(&p->t1), tmp_b},
+              {reinterpret_cast<void **>(&p->t2), tmp_b},
+              {&p->acc, grid_b},
+              {reinterpret_cast<void **>(&p->partials), kMaxPartials * sizeof(double)}};
+  for (auto &r : reqs) {
+    if (test_fail_alloc()) {
+      free_plan(p);
+      delete p;
+      return fail(SPFEL_ENOMEM, "plan_create: device allocation failed (forced by SPFEL_TEST_FAIL_ALLOC)");
+    }
+    e = hipMalloc(r.ptr, r.bytes);
+    if (e != hipSuccess) {
+      *r.ptr = nullptr;
+      (void)hipGetLastError();
+      free_plan(p);
+      delete p;
+      return fail(SPFEL_ENOMEM, std::string("plan_create: hipMalloc: ") + hipGetErrorString(e));
+    }
+    p->bytes += r.bytes;
+  }
+  // Transform tables in float64, rounded once to float32.  The phase index
+  // k l is reduced modulo nf exactly before the trigonometric evaluation.
+  std::vector<double> ph(N);
+  kernel_transform(n_model, p->nf, kernel_width, p->beta, ph.data());
+  const int h = (n_model - 1) / 2;
+  std::vector<float2> wp(N * nf), wn(nf * N);
+  for (int ki = 0; ki < n_model; ++ki) {
+    const long k = ki - h;
+    for (int l = 0; l < p->nf; ++l) {
+      long r = (k * l) % (long)nf;
+      if (r < 0) r += nf;
+      const double a = 2.0 * M_PI * (double)r / (double)nf;
+      const double c = std::cos(a) / ph[ki], s = std::sin(a) / ph[ki];
+      wp[(size_t)ki * nf + l] = make_float2((float)c, (float)s);
+      wn[(size_t)l * N + ki] = make_float2((float)c, (float)-s);
+    }
+  }
+  e = hipMemcpy(p->wpos, wp.data(), tab_b, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->wneg, wn.data(), tab_b, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(p);
+    delete p;
+    return hip_fail(e, "plan_create: table upload");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(p);
+  }
+  *out = reinterpret_cast<spfel_plan>(p);
+  return SPFEL_OK;
+}
+
+int spfel_plan_destroy(spfel_plan plan) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!p || g_live.erase(p) == 0) return fail(SPFEL_ESTATE, "plan_destroy: not a live plan");
+  }
+  DeviceGuard g(p->device);
+  free_plan(p);
+  delete p;
+  return SPFEL_OK;
+}
+
+int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "plan_info: not a live plan");
+  if (n_fine) *n_fine = p->nf;
+  if (device_bytes) *device_bytes = p->bytes;
+  return SPFEL_OK;
+}
+
+int spfel_set_model(spfel_plan plan, const void *model, void *stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "set_model: not a live plan");
+  if (!model) return fail(SPFEL_EINVAL, "set_model: model is NULL");
+  const bool cplx = p->domain == SPFEL_COMPLEX;
+  if (!aligned(model, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "set_model: model misaligned");
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "set_model: hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int N = p->N, nf = p->nf;
+  // u[l] = sum_k m_k exp(+2 pi i k.l / nf) / (psi_hat psi_hat psi_hat), one
+  // axis at a time: axis 2 (N^2 lines), axis 1, axis 0.
+  hipError_t e = launch_contract(model, cplx, p->wpos, p->t1, 0, N * N, N, nf, 1, s);
+  if (e == hipSuccess) e = launch_contract(p->t1, true, p->wpos, p->t2, 0, N, N, nf, nf, s);
+  if (e == hipSuccess) e = launch_contract(p->t2, true, p->wpos, p->u, cplx ? 0 : 1, 1, N, nf, nf * nf, s);
+  if (e != hipSuccess) return hip_fail(e, "set_model: launch");
+  p->model_set = true;
+  return SPFEL_OK;
+}
+
+int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
+                const float *det_q, int64_t P, void *out, uint16_t *out_bf16,
+                float *out_norm2, void *stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "slice: not a live plan");
+  if (!p->model_set) return fail(SPFEL_ESTATE, "slice: set_model has not been called");
+  if (M < 0 || P < 0) return fail(SPFEL_EINVAL, "slice: negative size");
+  const bool cplx = p->domain == SPFEL_COMPLEX;
+  if (M == 0) return SPFEL_OK;
+  if (P == 0) {
+    if (out_norm2 && !aligned(out_norm2, 4)) return fail(SPFEL_EINVAL, "slice: out_norm2 misaligned");
+    DeviceGuard g0(p->device);
+    if (g0.err != hipSuccess) return hip_fail(g0.err, "slice: hipSetDevice");
+    hipError_t e0 = out_norm2 ? launch_fill_zero(out_norm2, (size_t)M * sizeof(float),
+                                                 static_cast<hipStream_t>(stream))
+                              : hipSuccess;
+    return e0 == hipSuccess ? SPFEL_OK : hip_fail(e0, "slice: launch");
+  }
+  if (!out && !out_bf16 && !out_norm2) return fail(SPFEL_EINVAL, "slice: no output requested");
+  if (out_bf16 && cplx) return fail(SPFEL_EUNSUPPORTED, "slice: bfloat16 output is REAL-domain only");
+  if (!quats || !det_q) return fail(SPFEL_EINVAL, "slice: quats or det_q is NULL");
+  if (!aligned(quats, 4) || !aligned(det_q, 4)) return fail(SPFEL_EINVAL, "slice: input misaligned");
+  if (out && !aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "slice: out misaligned");
+  if (out_bf16 && !aligned(out_bf16, 2)) return fail(SPFEL_EINVAL, "slice: out_bf16 misaligned");
+  if (out_norm2 && !aligned(out_norm2, 4)) return fail(SPFEL_EINVAL, "slice: out_norm2 misaligned");
+  if (M > (int64_t)1 << 31 || P > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "slice: M or P too large");
+  if (out_norm2 && !out && !out_bf16) return fail(SPFEL_EINVAL, "slice: norms need out or out_bf16");
+  if (out_norm2 && !out && cplx) return fail(SPFEL_EINVAL, "slice: COMPLEX norms need out");
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "slice: hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_interp(*p, quats, M, det_q, P, out, out_bf16, s);
+  if (e == hipSuccess && out_norm2) {
+    if (out && !cplx)
+      e = launch_row_norm2(out, false, M, P, out_norm2, s);
+    else if (out && cplx)
+      e = launch_row_norm2(out, false, M, 2 * P, out_norm2, s);
+    else
+      e = launch_row_norm2(out_bf16, true, M, P, out_norm2, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "slice: launch");
+  return SPFEL_OK;
+}
+
+int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
+                    float *out, void *stream) {
+  clear_error();
+  if (rows < 0 || cols < 0) return fail(SPFEL_EINVAL, "row_norm2: negative size");
+  if (dtype != SPFEL_F32 && dtype != SPFEL_BF16) return fail(SPFEL_EINVAL, "row_norm2: dtype");
+  if (rows == 0) return SPFEL_OK;
+  if (!out || (!x && cols > 0)) return fail(SPFEL_EINVAL, "row_norm2: NULL pointer");
+  if (!aligned(out, 4) || (x && !aligned(x, dtype == SPFEL_F32 ? 4 : 2)))
+    return fail(SPFEL_EINVAL, "row_norm2: misaligned");
+  if (rows > (int64_t)1 << 31) return fail(SPFEL_ERANGE, "row_norm2: too many rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = cols == 0 ? launch_fill_zero(out, (size_t)rows * 4, s)
+                           : launch_row_norm2(x, dtype == SPFEL_BF16, rows, cols, out, s);
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "row_norm2: launch");
+}
+
+size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode) {
+  (void)P;
+  if (M < 0 || n_img < 0) return 0;
+  size_t b = (size_t)n_img * sizeof(unsigned long long);
+  if (mode == SPFEL_MATCH_BF16_RESCORE8) b = match_bf16_candidate_bytes(M, n_img);
+  return b < 256 ? 256 : b;
+}
+
+int spfel_match(const void *slices, const float *slice_norm2,
+                const void *images, const float *image_norm2, int64_t M,
+                int64_t n_img, int64_t P, int64_t m_offset, int mode,
+                const float *slices_f32, const float *images_f32,
+                int32_t *best_idx, float *best_dist, void *workspace,
+                size_t workspace_bytes, void *stream) {
+  clear_error();
+  if (M < 0 || n_img < 0 || P < 0 || m_offset < 0) return fail(SPFEL_EINVAL, "match: negative size");
+  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8)
+    return fail(SPFEL_EINVAL, "match: unknown mode");
+  if (m_offset + M > 0x7fffffffLL) return fail(SPFEL_ERANGE, "match: model index exceeds int32");
+  if (P > (int64_t)1 << 30 || n_img > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "match: size too large");
+  if (M == 0 || n_img == 0) return SPFEL_OK;
+  if (!slices || !images || !slice_norm2 || !image_norm2 || !best_idx || !best_dist)
+    return fail(SPFEL_EINVAL, "match: NULL pointer");
+  const bool bf = mode == SPFEL_MATCH_BF16_RESCORE8;
+  if (bf && (!slices_f32 || !images_f32))
+    return fail(SPFEL_EINVAL, "match: BF16 rescoring needs slices_f32 and images_f32");
+  if (!aligned(slices, bf ? 2 : 4) || !aligned(images, bf ? 2 : 4) || !aligned(slice_norm2, 4) ||
+      !aligned(image_norm2, 4) || !aligned(best_idx, 4) || !aligned(best_dist, 4) ||
+      (bf && (!aligned(slices_f32, 4) || !aligned(images_f32, 4))))
+    return fail(SPFEL_EINVAL, "match: misaligned pointer");
+  const size_t need = spfel_match_workspace_bytes(M, n_img, P, mode);
+  if (!workspace || workspace_bytes < need)
+    return fail(SPFEL_EINVAL, "match: workspace smaller than spfel_match_workspace_bytes");
+  if (!aligned(workspace, 16)) return fail(SPFEL_EINVAL, "match: workspace not 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (!bf) {
+    auto *keys = static_cast<unsigned long long *>(workspace);
+    e = launch_pack_keys(best_idx, best_dist, keys, n_img, s);
+    if (e == hipSuccess)
+      e = launch_match_f32(static_cast<const float *>(slices), static_cast<const float *>(images),
+                           slice_norm2, image_norm2, M, n_img, P, m_offset, keys, s);
+    if (e == hipSuccess) e = launch_unpack_keys(keys, best_idx, best_dist, n_img, s);
+  } else {
+    auto *cand = static_cast<uint32_t *>(workspace);
+    e = launch_match_bf16(static_cast<const uint16_t *>(slices), static_cast<const uint16_t *>(images),
+                          slice_norm2, image_norm2, M, n_img, P, cand, s);
+    if (e == hipSuccess)
+      e = launch_rescore(cand, M, n_img, P, m_offset, slices_f32, images_f32, slice_norm2,
+                         image_norm2, best_idx, best_dist, s);
+  }
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "match: launch");
+}
+
+int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
+                        const float *det_q, int64_t P, const void *values,
+                        const float *weights, void *out, int flags,
+                        void *stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "merge_adjoint: not a live plan");
+  if (n_img < 0 || P < 0) return fail(SPFEL_EINVAL, "merge_adjoint: negative size");
+  if (flags & ~(SPFEL_MERGE_ACCUMULATE | SPFEL_MERGE_DEFER))
+    return fail(SPFEL_EINVAL, "merge_adjoint: unknown flag");
+  const bool defer = (flags & SPFEL_MERGE_DEFER) != 0;
+  const bool cplx = p->domain == SPFEL_COMPLEX;
+  if (!defer && !out) return fail(SPFEL_EINVAL, "merge_adjoint: out is NULL");
+  if (out && !aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "merge_adjoint: out misaligned");
+  const bool any = n_img > 0 && P > 0;
+  if (any) {
+    if (!quats || !det_q || !values) return fail(SPFEL_EINVAL, "merge_adjoint: NULL input");
+    if (!aligned(quats, 4) || !aligned(det_q, 4) || !aligned(values, cplx ? 8 : 4) ||
+        (weights && !aligned(weights, 4)))
+      return fail(SPFEL_EINVAL, "merge_adjoint: input misaligned");
+    if (n_img > (int64_t)1 << 31 || P > (int64_t)1 << 30)
+      return fail(SPFEL_ERANGE, "merge_adjoint: size too large");
+  }
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "merge_adjoint: hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nf = p->nf;
+  const size_t grid_b = nf * nf * nf * (cplx ? sizeof(float2) : sizeof(float));
+  hipError_t e = hipSuccess;
+  if (!p->pending) e = launch_fill_zero(p->acc, grid_b, s);
+  if (e == hipSuccess && any) e = launch_spread(*p, quats, n_img, det_q, P, values, weights, s);
+  if (e != hipSuccess) return hip_fail(e, "merge_adjoint: launch");
+  p->pending = true;
+  if (defer) return SPFEL_OK;
+  p->pending = false;
+  const int N = p->N, nfi = p->nf;
+  const bool acc = (flags & SPFEL_MERGE_ACCUMULATE) != 0;
+  // f_k = sum_l v_l exp(-2 pi i k.l / nf) / (psi_hat psi_hat psi_hat),
+  // truncated to the N^3 modes: axis 2, axis 1, axis 0.
+  e = launch_contract(p->acc, cplx, p->wneg, p->t1, 0, nfi * nfi, nfi, N, 1, s);
+  if (e == hipSuccess) e = launch_contract(p->t1, true, p->wneg, p->t2, 0, nfi, nfi, N, N, s);
+  if (e == hipSuccess)
+    e = launch_contract(p->t2, true, p->wneg, out, cplx ? (acc ? 3 : 0) : (acc ? 2 : 1), 1, nfi, N, N * N, s);
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "merge_adjoint: launch");
+}
+
+int spfel_weighted_residual(spfel_plan plan, const void *slices,
+                            const void *images, const float *weights,
+                            int64_t count, float scale, void *residual,
+                            double *loss, void *stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "weighted_residual: not a live plan");
+  if (count < 0) return fail(SPFEL_EINVAL, "weighted_residual: negative count");
+  if (!residual && !loss) return fail(SPFEL_EINVAL, "weighted_residual: no output requested");
+  if (count == 0) return SPFEL_OK;
+  const bool cplx = p->domain == SPFEL_COMPLEX;
+  if (!slices || !images) return fail(SPFEL_EINVAL, "weighted_residual: NULL input");
+  const size_t a = cplx ? 8 : 4;
+  if (!aligned(slices, a) || !aligned(images, a) || (residual && !aligned(residual, a)) ||
+      (weights && !aligned(weights, 4)) || (loss && !aligned(loss, 8)))
+    return fail(SPFEL_EINVAL, "weighted_residual: misaligned pointer");
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "weighted_residual: hipSetDevice");
+  hipError_t e = launch_residual(cplx, slices, images, weights, count, scale, residual,
+                                 p->partials, loss, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "weighted_residual: launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Device helpers shared by the slicing, spreading and matching kernels:
+// orientation matrices, the kernel-support split of a fine-grid coordinate,
+// the ES kernel weights, bfloat16 rounding and order-preserving keys.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spfel {
+
+// Rotation matrix (row-major) of quaternion (w, x, y, z), Hamilton
+// convention, normalised by dividing by |q|^2; false for a zero or
+// non-finite quaternion.
+__device__ inline bool quat_rot(const float *__restrict__ q4, double R[9]) {
+  const double w = q4[0], x = q4[1], y = q4[2], z = q4[3];
+  const double n2 = w * w + x * x + y * y + z * z;
+  if (!(n2 > 0.0) || !(n2 < 1e300)) return false;
+  const double s = 2.0 / n2;
+  R[0] = 1.0 - s * (y * y + z * z);
+  R[1] = s * (x * y - w * z);
+  R[2] = s * (x * z + w * y);
+  R[3] = s * (x * y + w * z);
+  R[4] = 1.0 - s * (x * x + z * z);
+  R[5] = s * (y * z - w * x);
+  R[6] = s * (x * z - w * y);
+  R[7] = s * (y * z + w * x);
+  R[8] = 1.0 - s * (x * x + y * y);
+  return true;
+}
+
+// Fine-grid coordinate t (cells) -> first support cell l0 = ceil(t - W/2)
+// reduced modulo nf into [0, nf), and the offset frac = t - l0 in
+// (W/2 - 1, W/2].  False if t is not finite or absurdly large.
+template <int W>
+__device__ inline bool support_split(double t, int nf, int &base, float &frac) {
+  if (!(fabs(t) < 1e9)) return false;
+  const double l0 = ceil(t - 0.5 * W);
+  frac = (float)(t - l0);
+  double b = l0 - (double)nf * floor(l0 / (double)nf);
+  int bi = (int)b;
+  if (bi >= nf) bi -= nf;
+  if (bi < 0) bi += nf;
+  base = bi;
+  return true;
+}
+
+// ES kernel weights psi(frac - a), a = 0..W-1, with
+// psi(tau) = exp(beta (sqrt(1 - (2 tau / W)^2) - 1)).
+template <int W>
+__device__ inline void es_weights(float frac, float beta, float (&wt)[W]) {
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    const float z = (frac - (float)a) * (2.0f / (float)W);
+    const float r = fmaxf(1.0f - z * z, 0.0f);
+    wt[a] = __expf(beta * (sqrtf(r) - 1.0f));
+  }
+}
+
+// float -> bfloat16 bits, round to nearest, ties to even (NaN stays NaN).
+__device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Order-preserving map float -> uint32 (a < b  <=>  key(a) < key(b)).
+__device__ inline uint32_t float_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+}  // namespace spfel

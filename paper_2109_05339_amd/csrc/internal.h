@@ -1,0 +1,97 @@
+// Internal declarations of libspfel: the plan, status plumbing and the
+// host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "spfel.h"
+
+namespace spfel {
+
+// A plan owns everything slicing and merging need for one model size.
+struct Plan {
+  int device = 0;
+  int N = 0;          // model modes per axis (odd)
+  int nf = 0;         // fine grid cells per axis (2N)
+  int w = 0;          // kernel width in cells
+  int domain = SPFEL_REAL;
+  double beta = 0.0;  // kernel shape
+  // Fine grid the interpolation reads: nf^3 float (REAL) or float2 (COMPLEX).
+  void *u = nullptr;
+  // Separable transform tables, float2, row-major [L][K] for a contraction
+  // over L producing K:
+  //   wpos [N][nf]: exp(+2 pi i k l / nf) / psi_hat(k)   (model -> grid)
+  //   wneg [nf][N]: exp(-2 pi i k l / nf) / psi_hat(k)   (grid -> modes)
+  float2 *wpos = nullptr;
+  float2 *wneg = nullptr;
+  // Intermediates of the separable transforms, 4 N^3 float2 each.
+  float2 *t1 = nullptr;
+  float2 *t2 = nullptr;
+  // Spreading accumulator: nf^3 float (REAL) or float2 (COMPLEX).
+  void *acc = nullptr;
+  // Per-block partial sums of the weighted-residual loss.
+  double *partials = nullptr;
+  bool model_set = false;
+  bool pending = false;  // deferred spreads are waiting in acc
+  size_t bytes = 0;
+};
+
+// Status helpers: set the thread-local message and return the code.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+// psi_hat(k) for k = -h..h (host, float64): Fourier transform of the kernel
+// at mode k on a grid of nf cells.
+void kernel_transform(int N, int nf, int w, double beta, double *out);
+
+constexpr int kMaxPartials = 1024;
+
+// ---- launchers (return hipSuccess or the launch error) ----
+// Y[a][k][b] = sum_l X[a][l][b] W[l][k] (X float or float2 per x_complex);
+// out_mode: 0 store float2, 1 store real part (float), 2 add real part,
+// 3 add float2.
+hipError_t launch_contract(const void *X, bool x_complex, const float2 *W,
+                           void *Y, int out_mode, int A, int L, int K, int B,
+                           hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M,
+                         const float *detq, int64_t P, void *out,
+                         uint16_t *out_bf16, hipStream_t s);
+hipError_t launch_row_norm2(const void *x, bool bf16, int64_t rows,
+                            int64_t cols, float *out, hipStream_t s);
+
+hipError_t launch_spread(const Plan &pl, const float *quats, int64_t n_img,
+                         const float *detq, int64_t P, const void *values,
+                         const float *weights, hipStream_t s);
+
+hipError_t launch_pack_keys(const int32_t *idx, const float *dist,
+                            unsigned long long *keys, int64_t n,
+                            hipStream_t s);
+hipError_t launch_unpack_keys(const unsigned long long *keys, int32_t *idx,
+                              float *dist, int64_t n, hipStream_t s);
+hipError_t launch_match_f32(const float *S, const float *D, const float *sn,
+                            const float *dn, int64_t M, int64_t N, int64_t P,
+                            int64_t m_offset, unsigned long long *keys,
+                            hipStream_t s);
+size_t match_bf16_candidate_bytes(int64_t M, int64_t N);
+hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D,
+                             const float *sn, const float *dn, int64_t M,
+                             int64_t N, int64_t P, uint32_t *cand,
+                             hipStream_t s);
+hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N,
+                          int64_t P, int64_t m_offset, const float *S32,
+                          const float *D32, const float *sn, const float *dn,
+                          int32_t *best_idx, float *best_dist, hipStream_t s);
+
+hipError_t launch_residual(bool cplx, const void *s, const void *d,
+                           const float *w, int64_t count, float scale,
+                           void *r, double *partials, double *loss,
+                           hipStream_t st);
+
+}  // namespace spfel

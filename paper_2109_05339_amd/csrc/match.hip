@@ -1,0 +1,475 @@
+// Orientation matching (section II-B): every image against every model
+// image, D[m, n] = |s_m|^2 + |d_n|^2 - 2 s_m . d_n, nearest model wins.
+//
+// The cross term is a GEMM S (M x P) . D^T (P x n_img) on the matrix cores;
+// the M x n_img distance matrix is never stored: each 128 x 128 tile reduces
+// its columns in registers/LDS and publishes one result per image.
+//   FP32: v_mfma_f32_32x32x2_f32, per-tile column argmin, then a 64-bit
+//         atomicMin of (order-preserving distance key << 32 | model index),
+//         so the lowest index wins ties across tiles and across calls.
+//   BF16: v_mfma_f32_32x32x16_bf16 with float32 accumulation, per-tile column
+//         top-8 of the proxy distance; a second kernel merges the tiles'
+//         candidates per image and rescores the 8 in float32.
+#include "device_common.h"
+#include "internal.h"
+
+namespace spfel {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBM = 128;   // model images per tile
+constexpr int kBN = 128;   // images per tile
+constexpr int kGroup = 8;  // m-tiles per launch-order group
+
+// Tile of a block: blocks are dealt round-robin to the 8 XCDs, so the block
+// id is first remapped to make each XCD's blocks a contiguous range, and
+// that range is walked m-fastest in groups of kGroup m-tiles, so the blocks
+// resident on one XCD share slabs of S and D in that XCD's L2.
+__device__ inline void tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn) {
+  const int G = gridDim.x, bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3, per = G >> 3, rem = G & 7;
+  const int v = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  const int gsize = kGroup * tiles_n;
+  const int g = v / gsize;
+  const int first = g * kGroup;
+  const int gm = min(tiles_m - first, kGroup);
+  const int w = v - g * gsize;
+  tm = first + w % gm;
+  tn = w / gm;
+}
+
+// ---------------------------------------------------------------- FP32 ----
+constexpr int kBK = 32;         // floats of P per K step
+constexpr int kLdF = kBK + 4;   // LDS row stride (floats)
+
+__device__ inline float4 load_row4(const float *__restrict__ X, int64_t rows, int64_t r,
+                                   int64_t P, int64_t k, bool vec) {
+  if (r >= rows) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const float *p = X + r * P + k;
+  if (vec) return k < P ? *reinterpret_cast<const float4 *>(p) : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 v;
+  v.x = k < P ? p[0] : 0.f;
+  v.y = k + 1 < P ? p[1] : 0.f;
+  v.z = k + 2 < P ? p[2] : 0.f;
+  v.w = k + 3 < P ? p[3] : 0.f;
+  return v;
+}
+
+__global__ __launch_bounds__(256, 2) void match_f32_kernel(
+    const float *__restrict__ S, const float *__restrict__ D, const float *__restrict__ sn,
+    const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t m_offset,
+    unsigned long long *__restrict__ keys, int tiles_m, int tiles_n, int vec) {
+  __shared__ __attribute__((aligned(16))) float As[kBM * kLdF];
+  __shared__ __attribute__((aligned(16))) float Bs[kBN * kLdF];
+  __shared__ float sns[kBM], dns[kBN];
+  __shared__ unsigned long long red[2][kBN];
+
+  int tm, tn;
+  tile_of_block(tiles_m, tiles_n, tm, tn);
+  const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+
+  float4 ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 4;
+      ra[i] = load_row4(S, M, row0 + r, P, k0 + c, vec);
+      rb[i] = load_row4(D, N, col0 + r, P, k0 + c, vec);
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  for (int64_t k0 = 0; k0 < P; k0 += kBK) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 4;
+      *reinterpret_cast<float4 *>(&As[r * kLdF + c]) = ra[i];
+      *reinterpret_cast<float4 *>(&Bs[r * kLdF + c]) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kBK < P) gload(k0 + kBK);
+    // Fresh partial sums per K step keep every accumulation chain short:
+    // at most 2 kBK roundings inside the step plus one per step.
+    floatx16 part[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[i][j][r] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < kBK / 8; ++kk) {
+      float4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const float4 *>(&As[(wm * 64 + i * 32 + lr) * kLdF + kk * 8 + lh * 4]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const float4 *>(&Bs[(wn * 64 + j * 32 + lr) * kLdF + kk * 8 + lh * 4]);
+      // Lane half lh supplies k = 4 lh + e for MFMA e: A and B use the same
+      // permutation of the 8 k values, so the sum is unchanged.
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            part[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], b[j][e], part[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] += part[i][j];
+  }
+
+  if (tid < kBM) {
+    sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
+  } else {
+    const int c = tid - kBM;
+    dns[c] = col0 + c < N ? dn[col0 + c] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int cl = wn * 64 + j * 32 + lr;
+    unsigned long long best = ~0ull;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        // 32x32 MFMA output layout: lane holds column lane % 32 and rows
+        // 8 (r / 4) + 4 (lane / 32) + r % 4.
+        const int rl = wm * 64 + i * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+        if (row0 + rl < M) {
+          const float d = fmaf(-2.0f, acc[i][j][r], sns[rl] + dns[cl]);
+          const unsigned long long key =
+              ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)(row0 + rl));
+          best = key < best ? key : best;
+        }
+      }
+    const unsigned long long o = __shfl_xor(best, 32);
+    best = o < best ? o : best;
+    if (lh == 0) red[wm][cl] = best;
+  }
+  __syncthreads();
+  if (tid < kBN) {
+    const unsigned long long a = red[0][tid], b = red[1][tid];
+    const unsigned long long k = a < b ? a : b;
+    if (col0 + tid < N && k != ~0ull) atomicMin(keys + col0 + tid, k);
+  }
+}
+
+__global__ void pack_keys_kernel(const int32_t *__restrict__ idx, const float *__restrict__ dist,
+                                 unsigned long long *__restrict__ keys, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = ((unsigned long long)float_key(dist[i]) << 32) | (uint32_t)idx[i];
+}
+
+__global__ void unpack_keys_kernel(const unsigned long long *__restrict__ keys,
+                                   int32_t *__restrict__ idx, float *__restrict__ dist, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const unsigned long long k = keys[i];
+    idx[i] = (int32_t)(uint32_t)(k & 0xffffffffu);
+    dist[i] = key_float((uint32_t)(k >> 32));
+  }
+}
+
+hipError_t launch_pack_keys(const int32_t *idx, const float *dist, unsigned long long *keys,
+                            int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(pack_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx,
+                     dist, keys, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_keys(const unsigned long long *keys, int32_t *idx, float *dist, int64_t n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(unpack_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys,
+                     idx, dist, n);
+  return hipGetLastError();
+}
+
+static bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+hipError_t launch_match_f32(const float *S, const float *D, const float *sn, const float *dn,
+                            int64_t M, int64_t N, int64_t P, int64_t m_offset,
+                            unsigned long long *keys, hipStream_t s) {
+  const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
+  const int64_t blocks = (int64_t)tiles_m * tiles_n;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int vec = (P % 4 == 0) && al16(S) && al16(D);
+  hipLaunchKernelGGL(match_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M, N,
+                     P, (uint32_t)m_offset, keys, tiles_m, tiles_n, vec);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- BF16 ----
+constexpr int kBKH = 64;          // bf16 values of P per K step
+constexpr int kLdH = kBKH + 8;    // LDS row stride (bf16 values)
+
+__device__ inline uint4 load_row8h(const uint16_t *__restrict__ X, int64_t rows, int64_t r,
+                                   int64_t P, int64_t k, bool vec) {
+  if (r >= rows) return make_uint4(0u, 0u, 0u, 0u);
+  const uint16_t *p = X + r * P + k;
+  if (vec) return k < P ? *reinterpret_cast<const uint4 *>(p) : make_uint4(0u, 0u, 0u, 0u);
+  uint32_t h[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = k + e < P ? p[e] : 0u;
+  return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+// Sorted (ascending) insertion into a register top-8; branch free.
+__device__ inline void insert8(uint32_t (&top)[8], uint32_t x) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t lo = min(top[s], x);
+    x = max(top[s], x);
+    top[s] = lo;
+  }
+}
+__device__ inline void insert8(unsigned long long (&top)[8], unsigned long long x) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const unsigned long long lo = top[s] < x ? top[s] : x;
+    x = top[s] < x ? x : top[s];
+    top[s] = lo;
+  }
+}
+
+size_t match_bf16_candidate_bytes(int64_t M, int64_t N) {
+  const int64_t tiles_m = (M + kBM - 1) / kBM;
+  return (size_t)tiles_m * (size_t)N * 8 * sizeof(uint32_t);
+}
+
+// Candidate word: proxy-distance key with its 7 low bits replaced by the
+// row within the tile (a relative perturbation below 2^-16 of the proxy).
+__global__ __launch_bounds__(256, 2) void match_bf16_kernel(
+    const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
+    const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
+    int tiles_m, int tiles_n, int vec) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdH];
+  __shared__ float sns[kBM], dns[kBN];
+  __shared__ uint32_t red[2][kBN][8];
+
+  int tm, tn;
+  tile_of_block(tiles_m, tiles_n, tm, tn);
+  const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+
+  uint4 ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+      ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
+      rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  for (int64_t k0 = 0; k0 < P; k0 += kBKH) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+      *reinterpret_cast<uint4 *>(&As[r * kLdH + c]) = ra[i];
+      *reinterpret_cast<uint4 *>(&Bs[r * kLdH + c]) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kBKH < P) gload(k0 + kBKH);
+#pragma unroll
+    for (int kk = 0; kk < kBKH / 16; ++kk) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 64 + i * 32 + lr) * kLdH + kk * 16 + lh * 8]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 64 + j * 32 + lr) * kLdH + kk * 16 + lh * 8]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  if (tid < kBM) {
+    sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
+  } else {
+    const int c = tid - kBM;
+    dns[c] = col0 + c < N ? dn[col0 + c] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int cl = wn * 64 + j * 32 + lr;
+    uint32_t top[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) top[s] = ~0u;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rl = wm * 64 + i * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+        if (row0 + rl < M) {
+          const float b = fmaf(-2.0f, acc[i][j][r], sns[rl] + dns[cl]);
+          insert8(top, (float_key(b) & ~127u) | (uint32_t)rl);
+        }
+      }
+    uint32_t other[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) other[s] = __shfl_xor(top[s], 32);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) insert8(top, other[s]);
+    if (lh == 0) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) red[wm][cl][s] = top[s];
+    }
+  }
+  __syncthreads();
+  if (tid < kBN && col0 + tid < N) {
+    uint32_t top[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) top[s] = red[0][tid][s];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) insert8(top, red[1][tid][s]);
+    uint4 *dst = reinterpret_cast<uint4 *>(cand + ((int64_t)tm * N + col0 + tid) * 8);
+    dst[0] = make_uint4(top[0], top[1], top[2], top[3]);
+    dst[1] = make_uint4(top[4], top[5], top[6], top[7]);
+  }
+}
+
+hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *sn,
+                             const float *dn, int64_t M, int64_t N, int64_t P, uint32_t *cand,
+                             hipStream_t s) {
+  const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
+  const int64_t blocks = (int64_t)tiles_m * tiles_n;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int vec = (P % 8 == 0) && al16(S) && al16(D);
+  hipLaunchKernelGGL(match_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
+                     N, P, cand, tiles_m, tiles_n, vec);
+  return hipGetLastError();
+}
+
+// One wavefront per image: merge every tile's 8 candidates into the image's
+// 8 smallest proxies (ties: lowest model index), rescore those 8 exactly in
+// float32 against the float32 slices and image, and fold the best into the
+// caller's running (best_dist, best_idx).
+__global__ __launch_bounds__(256) void rescore_kernel(
+    const uint32_t *__restrict__ cand, int tiles_m, int64_t N, int64_t P, uint32_t m_offset,
+    const float *__restrict__ S32, const float *__restrict__ D32, const float *__restrict__ sn,
+    const float *__restrict__ dn, int32_t *__restrict__ best_idx, float *__restrict__ best_dist,
+    int vec) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= N) return;
+  unsigned long long top[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) top[s] = ~0ull;
+  const int total = tiles_m * 8;
+  for (int c = lane; c < total; c += 64) {
+    const int t = c >> 3, s = c & 7;
+    const uint32_t k = cand[((int64_t)t * N + n) * 8 + s];
+    if (k != ~0u) {
+      const uint32_t m = (uint32_t)t * kBM + (k & 127u);
+      insert8(top, ((unsigned long long)(k & ~127u) << 32) | m);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    unsigned long long other[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) other[s] = __shfl_xor(top[s], off);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) insert8(top, other[s]);
+  }
+  int mi[8];
+  bool valid[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    valid[s] = top[s] != ~0ull;
+    mi[s] = valid[s] ? (int)(uint32_t)(top[s] & 0xffffffffu) : 0;
+  }
+  float dot[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) dot[s] = 0.f;
+  const float *dimg = D32 + n * P;
+  if (vec) {
+    const int64_t P4 = P / 4;
+    for (int64_t q = lane; q < P4; q += 64) {
+      const float4 d = reinterpret_cast<const float4 *>(dimg)[q];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float4 v = reinterpret_cast<const float4 *>(S32 + (int64_t)mi[s] * P)[q];
+        dot[s] = fmaf(v.x, d.x, dot[s]);
+        dot[s] = fmaf(v.y, d.y, dot[s]);
+        dot[s] = fmaf(v.z, d.z, dot[s]);
+        dot[s] = fmaf(v.w, d.w, dot[s]);
+      }
+    }
+  } else {
+    for (int64_t p = lane; p < P; p += 64) {
+      const float d = dimg[p];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) dot[s] = fmaf(S32[(int64_t)mi[s] * P + p], d, dot[s]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) dot[s] += __shfl_xor(dot[s], off);
+  unsigned long long best = ~0ull;
+  const float dnn = dn[n];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    if (valid[s]) {
+      const float d = fmaf(-2.0f, dot[s], sn[mi[s]] + dnn);
+      const unsigned long long key =
+          ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)mi[s]);
+      best = key < best ? key : best;
+    }
+  }
+  if (lane == 0 && best != ~0ull) {
+    const unsigned long long run =
+        ((unsigned long long)float_key(best_dist[n]) << 32) | (uint32_t)best_idx[n];
+    if (best < run) {
+      best_idx[n] = (int32_t)(uint32_t)(best & 0xffffffffu);
+      best_dist[n] = key_float((uint32_t)(best >> 32));
+    }
+  }
+}
+
+hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N, int64_t P, int64_t m_offset,
+                          const float *S32, const float *D32, const float *sn, const float *dn,
+                          int32_t *best_idx, float *best_dist, hipStream_t s) {
+  const int tiles_m = (int)((M + kBM - 1) / kBM);
+  const int vec = (P % 4 == 0) && al16(S32) && al16(D32);
+  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, cand, tiles_m,
+                     N, P, (uint32_t)m_offset, S32, D32, sn, dn, best_idx, best_dist, vec);
+  return hipGetLastError();
+}
+
+}  // namespace spfel

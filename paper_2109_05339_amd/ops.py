@@ -1,0 +1,203 @@
+"""Python face of libspfel: argument marshalling only.
+
+Each function checks dtypes/devices/contiguity, passes raw device pointers
+and the current HIP stream to the C ABI of the same name, and returns the
+output tensors.  Every step of slicing, matching and merging runs in the
+library's kernels; PyTorch only owns the memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+REAL, COMPLEX = 0, 1
+F32, BF16 = 0, 1
+MATCH_FP32, MATCH_BF16_RESCORE8 = 0, 1
+MERGE_ACCUMULATE, MERGE_DEFER = 1, 2
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _p(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _need(t: torch.Tensor, name: str, dtype, device=None, shape=None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """Slicing/merging plan for an N^3 model (N odd) on one GPU."""
+
+    def __init__(self, n_model: int, kernel_width: int = 6, upsampfac: float = 2.0,
+                 beta_over_w: float = 2.30, domain: int = REAL, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.n_model = n_model
+        self.domain = domain
+        self.kernel_width = kernel_width
+        h = ctypes.c_void_p()
+        check(_lib.lib().spfel_plan_create(ctypes.byref(h), n_model, kernel_width, upsampfac,
+                                           beta_over_w, domain, dev.index))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def cdtype(self):
+        return torch.complex64 if self.domain == COMPLEX else torch.float32
+
+    def info(self):
+        nf = ctypes.c_int()
+        nb = ctypes.c_size_t()
+        check(_lib.lib().spfel_plan_info(self._h, ctypes.byref(nf), ctypes.byref(nb)))
+        return nf.value, nb.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            check(_lib.lib().spfel_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_model(self, model: torch.Tensor) -> None:
+        N = self.n_model
+        _need(model, "model", self.cdtype, self.device, (N, N, N))
+        check(_lib.lib().spfel_set_model(self._h, _p(model), _stream(self.device)))
+
+    def slice(self, quats: torch.Tensor, det_q: torch.Tensor, out: bool = True,
+              bf16: bool = False, norms: bool = False):
+        """Model images at orientations ``quats`` (M,4) and detector points
+        ``det_q`` (P,3).  Returns (slices or None, bf16 copy or None,
+        squared norms or None)."""
+        _need(quats, "quats", torch.float32, self.device)
+        _need(det_q, "det_q", torch.float32, self.device)
+        if quats.dim() != 2 or quats.shape[1] != 4 or det_q.dim() != 2 or det_q.shape[1] != 3:
+            raise ValueError("quats must be (M, 4) and det_q (P, 3)")
+        M, P = quats.shape[0], det_q.shape[0]
+        s = torch.empty((M, P), dtype=self.cdtype, device=self.device) if out else None
+        sb = torch.empty((M, P), dtype=torch.bfloat16, device=self.device) if bf16 else None
+        sn = torch.empty((M,), dtype=torch.float32, device=self.device) if norms else None
+        check(_lib.lib().spfel_slice(self._h, _p(quats), M, _p(det_q), P, _p(s), _p(sb), _p(sn),
+                                     _stream(self.device)))
+        return s, sb, sn
+
+    def merge_adjoint(self, quats: torch.Tensor, det_q: torch.Tensor, values: torch.Tensor,
+                      weights: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                      flags: int = 0) -> Optional[torch.Tensor]:
+        """Type-1 adjoint of the values (n_img, P) at the images' points,
+        onto N^3 modes.  With MERGE_DEFER only spreads (returns None)."""
+        _need(quats, "quats", torch.float32, self.device)
+        _need(det_q, "det_q", torch.float32, self.device)
+        n_img, P = quats.shape[0], det_q.shape[0]
+        _need(values, "values", self.cdtype, self.device, (n_img, P))
+        if weights is not None:
+            _need(weights, "weights", torch.float32, self.device, (n_img, P))
+        N = self.n_model
+        if out is None and not (flags & MERGE_DEFER):
+            out = torch.empty((N, N, N), dtype=self.cdtype, device=self.device)
+        elif out is not None:
+            _need(out, "out", self.cdtype, self.device, (N, N, N))
+        check(_lib.lib().spfel_merge_adjoint(self._h, _p(quats), n_img, _p(det_q), P, _p(values),
+                                             _p(weights), _p(out), flags, _stream(self.device)))
+        return out
+
+    def weighted_residual(self, slices: torch.Tensor, images: torch.Tensor,
+                          weights: Optional[torch.Tensor] = None, scale: float = 1.0,
+                          residual: bool = True, loss: Optional[torch.Tensor] = None):
+        """residual = scale w (s - d) (or None) and loss += sum w |s - d|^2
+        (a float64 device scalar, created if not given)."""
+        _need(slices, "slices", self.cdtype, self.device)
+        _need(images, "images", self.cdtype, self.device, tuple(slices.shape))
+        if weights is not None:
+            _need(weights, "weights", torch.float32, self.device, tuple(slices.shape))
+        if loss is None:
+            loss = torch.zeros((), dtype=torch.float64, device=self.device)
+        else:
+            _need(loss, "loss", torch.float64, self.device)
+        r = torch.empty_like(slices) if residual else None
+        check(_lib.lib().spfel_weighted_residual(self._h, _p(slices), _p(images), _p(weights),
+                                                 slices.numel(), float(scale), _p(r), _p(loss),
+                                                 _stream(self.device)))
+        return r, loss
+
+
+def row_norm2(x: torch.Tensor) -> torch.Tensor:
+    """Squared norms of the rows of a (rows, cols) float32/bfloat16 matrix."""
+    if x.dtype not in (torch.float32, torch.bfloat16):
+        raise TypeError("row_norm2 takes float32 or bfloat16")
+    _need(x, "x", x.dtype)
+    if x.dim() != 2:
+        raise ValueError("row_norm2 takes a matrix")
+    out = torch.empty((x.shape[0],), dtype=torch.float32, device=x.device)
+    check(_lib.lib().spfel_row_norm2(_p(x), BF16 if x.dtype == torch.bfloat16 else F32,
+                                     x.shape[0], x.shape[1], _p(out), _stream(x.device)))
+    return out
+
+
+def match_workspace_bytes(M: int, n_img: int, P: int, mode: int = MATCH_FP32) -> int:
+    return int(_lib.lib().spfel_match_workspace_bytes(M, n_img, P, mode))
+
+
+def new_best(n_img: int, device) -> tuple:
+    """Initial running best: (best_idx = -1, best_dist = +inf)."""
+    return (torch.full((n_img,), -1, dtype=torch.int32, device=device),
+            torch.full((n_img,), float("inf"), dtype=torch.float32, device=device))
+
+
+def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
+          image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
+          m_offset: int = 0, mode: int = MATCH_FP32, slices_f32: Optional[torch.Tensor] = None,
+          images_f32: Optional[torch.Tensor] = None,
+          workspace: Optional[torch.Tensor] = None) -> tuple:
+    """Fold the nearest model image of each image into (best_idx, best_dist)
+    in place and return them."""
+    dt = torch.bfloat16 if mode == MATCH_BF16_RESCORE8 else torch.float32
+    dev = slices.device
+    _need(slices, "slices", dt, dev)
+    _need(images, "images", dt, dev)
+    if slices.dim() != 2 or images.dim() != 2 or slices.shape[1] != images.shape[1]:
+        raise ValueError("slices (M, P) and images (n_img, P) must share P")
+    M, P = slices.shape
+    n_img = images.shape[0]
+    _need(slice_norm2, "slice_norm2", torch.float32, dev, (M,))
+    _need(image_norm2, "image_norm2", torch.float32, dev, (n_img,))
+    _need(best_idx, "best_idx", torch.int32, dev, (n_img,))
+    _need(best_dist, "best_dist", torch.float32, dev, (n_img,))
+    if mode == MATCH_BF16_RESCORE8:
+        _need(slices_f32, "slices_f32", torch.float32, dev, (M, P))
+        _need(images_f32, "images_f32", torch.float32, dev, (n_img, P))
+    need = match_workspace_bytes(M, n_img, P, mode)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=dev)
+    check(_lib.lib().spfel_match(_p(slices), _p(slice_norm2), _p(images), _p(image_norm2), M,
+                                 n_img, P, m_offset, mode, _p(slices_f32), _p(images_f32),
+                                 _p(best_idx), _p(best_dist), _p(workspace), workspace.numel(),
+                                 _stream(dev)))
+    return best_idx, best_dist

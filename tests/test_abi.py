@@ -1,0 +1,115 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol
+include/spfel.h declares, and rejects invalid arguments before any GPU work
+(these paths never reach a HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2109_05339_amd as spfel
+from paper_2109_05339_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "spfel.h")).read()
+    return sorted(set(re.findall(r"\b(spfel_\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree_and_symbols_exist():
+    names = header_functions()
+    assert len(names) >= 12
+    assert set(names) == set(_lib.SIGNATURES)
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+
+
+def test_version_and_empty_error():
+    L = spfel.lib()
+    assert L.spfel_version() == 100
+
+
+def _create(*args):
+    h = ctypes.c_void_p()
+    code = spfel.lib().spfel_plan_create(ctypes.byref(h), *args)
+    return code, h
+
+
+@pytest.mark.parametrize("args,code", [
+    ((32, 6, 2.0, 2.3, 0, 0), _lib.EINVAL),          # even N
+    ((1, 6, 2.0, 2.3, 0, 0), _lib.EINVAL),           # N < 3
+    ((5, 7, 2.0, 2.3, 0, 0), _lib.EINVAL),           # w > N
+    ((33, 3, 2.0, 2.3, 0, 0), _lib.EUNSUPPORTED),    # w outside 4..8
+    ((33, 6, 1.5, 2.3, 0, 0), _lib.EUNSUPPORTED),    # sigma != 2
+    ((33, 6, 2.0, -1.0, 0, 0), _lib.EINVAL),         # beta <= 0
+    ((33, 6, 2.0, 2.3, 7, 0), _lib.EINVAL),          # domain
+    ((513, 6, 2.0, 2.3, 0, 0), _lib.ERANGE),         # too large
+])
+def test_plan_create_validation(args, code):
+    c, h = _create(*args)
+    assert c == code
+    assert h.value is None
+    assert spfel.lib().spfel_last_error().decode() != ""
+
+
+def test_null_out_pointer():
+    assert spfel.lib().spfel_plan_create(None, 33, 6, 2.0, 2.3, 0, 0) == _lib.EINVAL
+
+
+def test_dead_plan_handles_are_rejected():
+    L = spfel.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.spfel_plan_destroy(None) == _lib.ESTATE
+    assert L.spfel_plan_destroy(bogus) == _lib.ESTATE
+    assert L.spfel_set_model(bogus, bogus, None) == _lib.ESTATE
+    assert L.spfel_slice(bogus, None, 1, None, 1, None, None, None, None) == _lib.ESTATE
+    assert L.spfel_merge_adjoint(bogus, None, 1, None, 1, None, None, None, 0, None) == _lib.ESTATE
+    assert L.spfel_weighted_residual(bogus, None, None, None, 1, 1.0, None, None, None) == _lib.ESTATE
+    assert L.spfel_plan_info(bogus, None, None) == _lib.ESTATE
+    with pytest.raises(spfel.SpfelStateError):
+        _lib.check(L.spfel_plan_destroy(bogus))
+
+
+def test_match_validation_before_launch():
+    L = spfel.lib()
+    p = ctypes.c_void_p(4096)
+    args = dict(slices=p, sn=p, images=p, dn=p, M=10, N=10, P=64, off=0, mode=0, s32=None,
+                d32=None, idx=p, dist=p, ws=p, wsb=1 << 20, st=None)
+
+    def call(**kw):
+        a = dict(args)
+        a.update(kw)
+        return L.spfel_match(a["slices"], a["sn"], a["images"], a["dn"], a["M"], a["N"], a["P"],
+                             a["off"], a["mode"], a["s32"], a["d32"], a["idx"], a["dist"], a["ws"],
+                             a["wsb"], a["st"])
+    assert call(M=-1) == _lib.EINVAL
+    assert call(mode=5) == _lib.EINVAL
+    assert call(off=2 ** 31 - 5) == _lib.ERANGE
+    assert call(slices=None) == _lib.EINVAL
+    assert call(mode=1) == _lib.EINVAL                        # no float32 data to rescore
+    assert call(wsb=8) == _lib.EINVAL                         # workspace too small
+    assert call(slices=ctypes.c_void_p(4098)) == _lib.EINVAL  # misaligned
+    assert call(M=0) == _lib.OK and call(N=0) == _lib.OK      # empty: nothing to do
+
+
+def test_workspace_sizes():
+    ws = spfel.match_workspace_bytes
+    assert ws(1000, 256, 4096, spfel.MATCH_FP32) == 256 * 8
+    assert ws(1000, 256, 4096, spfel.MATCH_BF16_RESCORE8) == 8 * 256 * 8 * 4   # 8 m-tiles of 128
+    assert ws(0, 0, 0, spfel.MATCH_FP32) == 256
+
+
+def test_row_norm2_validation():
+    L = spfel.lib()
+    assert L.spfel_row_norm2(None, 7, 1, 1, None, None) == _lib.EINVAL
+    assert L.spfel_row_norm2(None, 0, -1, 1, None, None) == _lib.EINVAL
+    assert L.spfel_row_norm2(None, 0, 0, 5, None, None) == _lib.OK
+    assert L.spfel_row_norm2(None, 0, 3, 5, None, None) == _lib.EINVAL
+
+
+def test_exceptions_map_codes():
+    with pytest.raises(spfel.SpfelInvalidArgument):
+        _lib.check(spfel.lib().spfel_row_norm2(None, 7, 1, 1, None, None))

@@ -1,0 +1,80 @@
+"""Differentiable slicing: the hand-written backward (type-1 spread) against
+the FP64 oracle's adjoint and gradient, and against finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2109_05339_amd as spfel
+from oracle import geometry, grad as ograd, nufft
+from tests._common import DEV, rel, gpu, host, detector, f32
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(N=13, n_img=6, n_det=16, seed=0):
+    g = np.random.default_rng(seed)
+    m = (g.standard_normal((N,) * 3) + 1j * g.standard_normal((N,) * 3)).astype(np.complex64)
+    q = synth.quaternions(synth.config(4), "image_quats", n_img)
+    det = detector(n_det)
+    x = geometry.slice_points(f32(q), f32(det)).reshape(-1, 3)
+    d = (nufft.nufft2(m.astype(np.complex128) * 1.1, x) + 0.05 * g.standard_normal(len(x))).astype(np.complex64)
+    w = synth.pixel_weights(synth.config(4), n_img, det.shape[0])
+    return m, q, det, x, d.reshape(n_img, -1), w
+
+
+def test_slicefn_backward_is_oracle_adjoint():
+    m, q, det, x, _, _ = setup()
+    plan = spfel.Plan(13, domain=spfel.COMPLEX, device=DEV)
+    mt = gpu(m, torch.complex64).requires_grad_(True)
+    s = spfel.slice_model(mt, gpu(q), gpu(det), plan)
+    g = np.random.default_rng(9)
+    gs = (g.standard_normal(s.shape) + 1j * g.standard_normal(s.shape)).astype(np.complex64)
+    s.backward(gpu(gs, torch.complex64))
+    ref = nufft.nufft1(gs.astype(np.complex128).ravel(), x, 13)
+    assert rel(host(mt.grad), ref) <= 1e-5
+
+
+def test_slice_loss_value_and_gradient():
+    m, q, det, x, d, w = setup()
+    plan = spfel.Plan(13, domain=spfel.COMPLEX, device=DEV)
+    mt = gpu(m, torch.complex64).requires_grad_(True)
+    L = spfel.slice_loss(mt, gpu(q), gpu(det), gpu(d, torch.complex64), gpu(w), plan, chunk=4)
+    L.backward()
+    m64 = m.astype(np.complex128)
+    Lref = ograd.loss(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel())
+    assert abs(float(L) - Lref) <= 1e-4 * Lref
+    gref = ograd.grad(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel())
+    assert rel(host(mt.grad), gref) <= 1e-4
+    vox = synth.fd_voxels(synth.config(4), 8) % (13 ** 3)
+    fd = ograd.fd_grad(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel(), vox, h=1e-3)
+    gg = host(mt.grad).reshape(-1)[vox]
+    assert np.max(np.abs(gg - fd)) <= 1e-3 * np.abs(gref).max()
+
+
+def test_chunking_does_not_change_the_gradient():
+    m, q, det, x, d, w = setup(n_img=9)
+    plan = spfel.Plan(13, domain=spfel.COMPLEX, device=DEV)
+    out = []
+    for chunk in (9, 2):
+        mt = gpu(m, torch.complex64).requires_grad_(True)
+        L = spfel.slice_loss(mt, gpu(q), gpu(det), gpu(d, torch.complex64), gpu(w), plan, chunk=chunk)
+        L.backward()
+        out.append((float(L), host(mt.grad)))
+    assert abs(out[0][0] - out[1][0]) <= 1e-6 * abs(out[0][0])
+    assert rel(out[1][1], out[0][1]) <= 1e-5
+
+
+def test_real_domain_gradient():
+    N = 9
+    g = np.random.default_rng(3)
+    m = g.standard_normal((N,) * 3).astype(np.float32)
+    q = synth.quaternions(synth.config(1), "image_quats", 4)
+    det = detector(10)
+    plan = spfel.Plan(N, device=DEV)
+    mt = gpu(m).requires_grad_(True)
+    s = spfel.slice_model(mt, gpu(q), gpu(det), plan)
+    gs = g.standard_normal(s.shape).astype(np.float32)
+    s.backward(gpu(gs))
+    x = geometry.slice_points(f32(q), f32(det)).reshape(-1, 3)
+    assert rel(host(mt.grad), nufft.nufft1(gs.astype(np.float64).ravel(), x, N, real=True)) <= 1e-5
