@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2, help="workload id (2: the default above)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip BF16 and spread side runs")
-    ap.add_argument("--cpu-sample", type=int, default=48, help="orientations in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=200, help="orientations in the oracle sample")
     return ap.parse_args()
 
 
@@ -72,8 +72,9 @@ def main() -> int:
     ref_q = torch.from_numpy(synth.quaternions(cfg, "ref_quats", M).astype(np.float32)).to(dev)
     img_q = torch.from_numpy(synth.quaternions(cfg, "image_quats", n_img).astype(np.float32)).to(dev)
     plan = spfel.Plan(N, device=dev)
+    plan.set_detector(det)
     plan.set_model(torch.from_numpy(m_host.astype(np.float32)).to(dev))
-    lam0 = plan.slice(img_q, det)[0].clamp_(min=0).cpu().numpy()
+    lam0 = plan.slice(img_q)[0].clamp_(min=0).cpu().numpy()
     alpha = synth.photon_scale(lam0, cfg.photons)
     images = torch.from_numpy(synth.poisson_counts(cfg, alpha * lam0)).to(dev)
     del lam0
@@ -93,7 +94,7 @@ def main() -> int:
         e = [ev() for _ in range(4)] if marks is not None else None
         if e: e[0].record(stream)
         plan.set_model(model)
-        S, _, sn = plan.slice(ref_q, det, out=True, norms=True)
+        S, _, sn = plan.slice(ref_q, out=True, norms=True)
         if e: e[1].record(stream)
         bi, bd = spfel.new_best(n_img, dev)
         if e: e[2].record(stream)
@@ -107,7 +108,7 @@ def main() -> int:
         e = [ev() for _ in range(4)] if marks is not None else None
         if e: e[0].record(stream)
         plan.set_model(model)
-        S, Sb, sn = plan.slice(ref_q, det, out=True, bf16=True, norms=True)
+        S, Sb, sn = plan.slice(ref_q, out=True, bf16=True, norms=True)
         if e: e[1].record(stream)
         bi, bd = spfel.new_best(n_img, dev)
         if e: e[2].record(stream)
@@ -193,13 +194,13 @@ def main() -> int:
         log(f"bf16 step {max(wall_b, step_b):.3f} ms (match {match_b:.3f}), agreement {agree:.4f}")
         # type-1 spread of every image at its matched orientation (merge A* b)
         mq = ref_q[bi32.long()].contiguous()
-        plan.merge_adjoint(mq, det, images)
+        plan.merge_adjoint(mq, None, images)
         torch.cuda.synchronize()
         a, b = ev(), ev()
         reps = 5
         a.record(stream)
         for _ in range(reps):
-            plan.merge_adjoint(mq, det, images)
+            plan.merge_adjoint(mq, None, images)
         b.record(stream)
         torch.cuda.synchronize()
         t1 = a.elapsed_time(b) / reps

@@ -88,6 +88,18 @@ int spfel_plan_destroy(spfel_plan plan);
  * may be NULL). */
 int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes);
 
+/* Register the detector template (section II-A: the model images are
+ * computed on a predetermined geometry; section IV-A: one flat detector).
+ * det_q: P x 3 float32 device points.  The plan keeps a copy sorted along a
+ * 3D Morton curve, so runs of 256 consecutive points are compact patches,
+ * and spfel_slice / spfel_merge_adjoint called with det_q = NULL (and the
+ * same P) use it: each (orientation, patch) then stages its fine-grid brick
+ * in LDS.  Outputs stay in the caller's pixel order.  This call copies the
+ * points to the host (it synchronises `stream`) and allocates device memory;
+ * it replaces any earlier registration. */
+int spfel_set_detector(spfel_plan plan, const float *det_q, int64_t P,
+                       void *stream);
+
 /* Section II-A, the model-side half of the type-2 NUFFT: deconvolve the
  * model by the kernel's Fourier transform, zero-pad to n_f^3 and transform
  * to the oversampled grid the interpolation reads.  `model` is N^3 float32
@@ -96,7 +108,8 @@ int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes);
 int spfel_set_model(spfel_plan plan, const void *model, void *stream);
 
 /* Section II-A: slice the model at M orientations.  quats: M x 4 float32;
- * det_q: P x 3 float32.  Outputs (each may be NULL, not all):
+ * det_q: P x 3 float32, or NULL for the registered detector (P must then
+ * equal the registered size).  Outputs (each may be NULL, not all):
  *   out       M x P row-major, float32 (REAL) or complex64 (COMPLEX);
  *   out_bf16  M x P bfloat16 (round to nearest even) copy, REAL only;
  *   out_norm2 M float32 squared norms |s_m|^2 (sum of |s|^2 over P).
@@ -138,7 +151,8 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 size_t workspace_bytes, void *stream);
 
 /* Section II-C, Eq. (2) right-hand side: the type-1 NUFFT (adjoint of
- * slicing) of values at the points R(quats[n]) det_q[p]:
+ * slicing) of values at the points R(quats[n]) det_q[p] (det_q NULL: the
+ * registered detector, values still in the caller's pixel order):
  *   REAL:    out_k = sum_{n,p} y_np cos(k . x_np)
  *   COMPLEX: out_k = sum_{n,p} y_np exp(-i k . x_np)
  * with y = values (n_img x P, float32 or complex64) times weights (n_img x P

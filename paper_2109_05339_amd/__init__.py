@@ -10,4 +10,5 @@ from .ops import (Plan, row_norm2, match, match_workspace_bytes, new_best,  # no
                   MERGE_DEFER)
 from .autograd import SliceFn, SliceLossFn, slice_model, slice_loss  # noqa: F401
 
-lib()  # fail loudly at import if the library is not built
+# The library is loaded on first use (lib()); a missing build raises
+# ImportError there.  There is no fallback path.

@@ -48,6 +48,7 @@ SIGNATURES = {
     "spfel_plan_create": (_int, [ctypes.POINTER(_vp), _int, _int, _dbl, _dbl, _int, _int]),
     "spfel_plan_destroy": (_int, [_vp]),
     "spfel_plan_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_sz)]),
+    "spfel_set_detector": (_int, [_vp, _vp, _i64, _vp]),
     "spfel_set_model": (_int, [_vp, _vp, _vp]),
     "spfel_slice": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp]),
     "spfel_row_norm2": (_int, [_vp, _int, _i64, _i64, _vp, _vp]),

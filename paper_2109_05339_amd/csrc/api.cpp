@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <new>
 #include <set>
 #include <string>
@@ -102,7 +104,8 @@ static bool aligned(const void *p, size_t a) {
 }
 
 static void free_plan(Plan *p) {
-  void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials};
+  void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials, p->det_sorted,
+                  p->det_perm};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -244,6 +247,90 @@ int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes) {
   return SPFEL_OK;
 }
 
+int spfel_set_detector(spfel_plan plan, const float *det_q, int64_t P, void *stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "set_detector: not a live plan");
+  if (P <= 0) return fail(SPFEL_EINVAL, "set_detector: P must be positive");
+  if (P > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "set_detector: P too large");
+  if (!det_q || !aligned(det_q, 4)) return fail(SPFEL_EINVAL, "set_detector: det_q NULL or misaligned");
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "set_detector: hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<float> h((size_t)P * 3);
+  hipError_t e = hipMemcpyAsync(h.data(), det_q, h.size() * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "set_detector: copy to host");
+  // 3D Morton key of each point on a 1024^3 lattice over the points' box;
+  // non-finite points sort last.
+  float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+  for (int64_t i = 0; i < P; ++i)
+    for (int d = 0; d < 3; ++d) {
+      const float v = h[3 * i + d];
+      if (std::isfinite(v)) {
+        lo[d] = std::min(lo[d], v);
+        hi[d] = std::max(hi[d], v);
+      }
+    }
+  auto spread_bits = [](uint32_t v) {
+    uint64_t x = v & 0x3ff;
+    x = (x | (x << 16)) & 0x030000FF;
+    x = (x | (x << 8)) & 0x0300F00F;
+    x = (x | (x << 4)) & 0x030C30C3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+  };
+  std::vector<uint64_t> key((size_t)P);
+  for (int64_t i = 0; i < P; ++i) {
+    uint64_t k = 0;
+    bool fin = true;
+    for (int d = 0; d < 3; ++d) {
+      const float v = h[3 * i + d];
+      if (!std::isfinite(v)) {
+        fin = false;
+        break;
+      }
+      const float span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0f;
+      int qv = (int)((v - lo[d]) / span * 1023.0f + 0.5f);
+      qv = std::min(std::max(qv, 0), 1023);
+      k |= spread_bits((uint32_t)qv) << d;
+    }
+    key[i] = fin ? k : ~0ull;
+  }
+  std::vector<int32_t> perm((size_t)P);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  std::vector<float> sorted((size_t)P * 3);
+  for (int64_t i = 0; i < P; ++i)
+    for (int d = 0; d < 3; ++d) sorted[3 * i + d] = h[3 * (size_t)perm[i] + d];
+  float *ds = nullptr;
+  int32_t *dp = nullptr;
+  e = hipMalloc(reinterpret_cast<void **>(&ds), sorted.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&dp), perm.size() * sizeof(int32_t));
+  if (e != hipSuccess) {
+    if (ds) (void)hipFree(ds);
+    (void)hipGetLastError();
+    return fail(SPFEL_ENOMEM, "set_detector: hipMalloc");
+  }
+  e = hipMemcpy(ds, sorted.data(), sorted.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dp, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ds);
+    (void)hipFree(dp);
+    return hip_fail(e, "set_detector: upload");
+  }
+  if (p->det_sorted) {
+    p->bytes -= (size_t)p->det_P * 3 * sizeof(float) + (size_t)p->det_P * sizeof(int32_t);
+    (void)hipFree(p->det_sorted);
+    (void)hipFree(p->det_perm);
+  }
+  p->det_sorted = ds;
+  p->det_perm = dp;
+  p->det_P = P;
+  p->bytes += sorted.size() * sizeof(float) + perm.size() * sizeof(int32_t);
+  return SPFEL_OK;
+}
+
 int spfel_set_model(spfel_plan plan, const void *model, void *stream) {
   clear_error();
   Plan *p = reinterpret_cast<Plan *>(plan);
@@ -286,8 +373,10 @@ int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
   }
   if (!out && !out_bf16 && !out_norm2) return fail(SPFEL_EINVAL, "slice: no output requested");
   if (out_bf16 && cplx) return fail(SPFEL_EUNSUPPORTED, "slice: bfloat16 output is REAL-domain only");
-  if (!quats || !det_q) return fail(SPFEL_EINVAL, "slice: quats or det_q is NULL");
-  if (!aligned(quats, 4) || !aligned(det_q, 4)) return fail(SPFEL_EINVAL, "slice: input misaligned");
+  if (!quats) return fail(SPFEL_EINVAL, "slice: quats is NULL");
+  if (!det_q && P != p->det_P)
+    return fail(SPFEL_EINVAL, "slice: det_q is NULL and P differs from the registered detector");
+  if (!aligned(quats, 4) || (det_q && !aligned(det_q, 4))) return fail(SPFEL_EINVAL, "slice: input misaligned");
   if (out && !aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "slice: out misaligned");
   if (out_bf16 && !aligned(out_bf16, 2)) return fail(SPFEL_EINVAL, "slice: out_bf16 misaligned");
   if (out_norm2 && !aligned(out_norm2, 4)) return fail(SPFEL_EINVAL, "slice: out_norm2 misaligned");
@@ -327,9 +416,8 @@ int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
 }
 
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode) {
-  (void)P;
-  if (M < 0 || n_img < 0) return 0;
-  size_t b = (size_t)n_img * sizeof(unsigned long long);
+  if (M < 0 || n_img < 0 || P < 0) return 0;
+  size_t b = match_f32_workspace_bytes(M, n_img, P);
   if (mode == SPFEL_MATCH_BF16_RESCORE8) b = match_bf16_candidate_bytes(M, n_img);
   return b < 256 ? 256 : b;
 }
@@ -367,7 +455,7 @@ int spfel_match(const void *slices, const float *slice_norm2,
     e = launch_pack_keys(best_idx, best_dist, keys, n_img, s);
     if (e == hipSuccess)
       e = launch_match_f32(static_cast<const float *>(slices), static_cast<const float *>(images),
-                           slice_norm2, image_norm2, M, n_img, P, m_offset, keys, s);
+                           slice_norm2, image_norm2, M, n_img, P, m_offset, workspace, s);
     if (e == hipSuccess) e = launch_unpack_keys(keys, best_idx, best_dist, n_img, s);
   } else {
     auto *cand = static_cast<uint32_t *>(workspace);
@@ -396,8 +484,10 @@ int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
   if (out && !aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "merge_adjoint: out misaligned");
   const bool any = n_img > 0 && P > 0;
   if (any) {
-    if (!quats || !det_q || !values) return fail(SPFEL_EINVAL, "merge_adjoint: NULL input");
-    if (!aligned(quats, 4) || !aligned(det_q, 4) || !aligned(values, cplx ? 8 : 4) ||
+    if (!quats || !values) return fail(SPFEL_EINVAL, "merge_adjoint: NULL input");
+    if (!det_q && P != p->det_P)
+      return fail(SPFEL_EINVAL, "merge_adjoint: det_q is NULL and P differs from the registered detector");
+    if (!aligned(quats, 4) || (det_q && !aligned(det_q, 4)) || !aligned(values, cplx ? 8 : 4) ||
         (weights && !aligned(weights, 4)))
       return fail(SPFEL_EINVAL, "merge_adjoint: input misaligned");
     if (n_img > (int64_t)1 << 31 || P > (int64_t)1 << 30)

@@ -35,10 +35,19 @@ struct Plan {
   void *acc = nullptr;
   // Per-block partial sums of the weighted-residual loss.
   double *partials = nullptr;
+  // Registered detector template (spfel_set_detector): points sorted along
+  // a 3D Morton curve so that every run of kTile consecutive points is a
+  // compact patch; det_perm maps a sorted position to the caller's pixel.
+  float *det_sorted = nullptr;   // det_P x 3
+  int32_t *det_perm = nullptr;   // det_P
+  int64_t det_P = 0;
   bool model_set = false;
   bool pending = false;  // deferred spreads are waiting in acc
   size_t bytes = 0;
 };
+
+// Points per detector tile of the tiled slicing/spreading kernels.
+constexpr int kTile = 256;
 
 // Status helpers: set the thread-local message and return the code.
 int fail(int code, const std::string &msg);
@@ -60,12 +69,14 @@ hipError_t launch_contract(const void *X, bool x_complex, const float2 *W,
                            hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
+// detq == nullptr selects the plan's registered detector (tiled kernel).
 hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M,
                          const float *detq, int64_t P, void *out,
                          uint16_t *out_bf16, hipStream_t s);
 hipError_t launch_row_norm2(const void *x, bool bf16, int64_t rows,
                             int64_t cols, float *out, hipStream_t s);
 
+// detq == nullptr selects the plan's registered detector (tiled kernel).
 hipError_t launch_spread(const Plan &pl, const float *quats, int64_t n_img,
                          const float *detq, int64_t P, const void *values,
                          const float *weights, hipStream_t s);
@@ -75,10 +86,13 @@ hipError_t launch_pack_keys(const int32_t *idx, const float *dist,
                             hipStream_t s);
 hipError_t launch_unpack_keys(const unsigned long long *keys, int32_t *idx,
                               float *dist, int64_t n, hipStream_t s);
+// workspace: packed keys (N u64) first, then split-K counters and partial
+// tiles when the launch splits K (match_f32_workspace_bytes).
+int match_f32_splits(int64_t M, int64_t N, int64_t P);
+size_t match_f32_workspace_bytes(int64_t M, int64_t N, int64_t P);
 hipError_t launch_match_f32(const float *S, const float *D, const float *sn,
                             const float *dn, int64_t M, int64_t N, int64_t P,
-                            int64_t m_offset, unsigned long long *keys,
-                            hipStream_t s);
+                            int64_t m_offset, void *workspace, hipStream_t s);
 size_t match_bf16_candidate_bytes(int64_t M, int64_t N);
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D,
                              const float *sn, const float *dn, int64_t M,

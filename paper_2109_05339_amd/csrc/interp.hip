@@ -1,6 +1,8 @@
 // Type-2 interpolation (slicing, section II-A): each model image pixel is
 // the ES-kernel-weighted sum of the w^3 fine-grid cells around its rotated
 // Ewald-sphere point, s(x) = sum_{a,b,c} u[l0 + (a,b,c)] psi psi psi.
+#include <type_traits>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -101,12 +103,218 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Tiled interpolation over the registered detector.  One block of kTile
+// threads takes one orientation and one detector tile (kTile Morton-sorted,
+// hence spatially compact, template points): the rotated points' support
+// cells span a small axis-aligned brick of the fine grid, which the block
+// stages in LDS with coalesced row reads; the w^3 gather then reads LDS
+// instead of L1/L2.  A brick larger than the LDS budget (possible only for
+// unusually spread tiles) makes the block gather from global memory.
+constexpr int kBrickBytes = 32768;
+
+__device__ inline int wrap_mod(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Block-wide min and max of three ints (kTile threads, 4 wavefronts).
+__device__ inline void block_minmax3(int (&mn)[3], int (&mx)[3], int (*sh)[6]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], __shfl_xor(mn[d], off));
+      mx[d] = max(mx[d], __shfl_xor(mx[d], off));
+    }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sh[wave][d] = mn[d];
+      sh[wave][3 + d] = mx[d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = min(min(sh[0][d], sh[1][d]), min(sh[2][d], sh[3][d]));
+    mx[d] = max(max(sh[0][3 + d], sh[1][3 + d]), max(sh[2][3 + d], sh[3][3 + d]));
+  }
+}
+
+template <int W, bool CPLX>
+__global__ __launch_bounds__(kTile) void interp_tiled_kernel(
+    const void *__restrict__ u_, int nf, float beta, const float *__restrict__ quats, int64_t M,
+    const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
+    void *__restrict__ out_, uint16_t *__restrict__ out_bf16) {
+  typedef typename std::conditional<CPLX, float2, float>::type T;
+  constexpr int kCap = kBrickBytes / (int)sizeof(T);
+  __shared__ __attribute__((aligned(16))) T brick[kCap];
+  __shared__ int red[4][6];
+  __shared__ int wrap[3][64];
+
+  const int64_t m = (int64_t)blockIdx.x / tiles;
+  const int tile = (int)((int64_t)blockIdx.x - m * tiles);
+  const int64_t i = (int64_t)tile * kTile + threadIdx.x;
+  const bool inb = i < P;
+  double R[9];
+  const bool qok = quat_rot(quats + 4 * m, R);
+  const double scale = (double)nf / (2.0 * M_PI);
+  int l0[3] = {0, 0, 0};
+  float frac[3] = {0.f, 0.f, 0.f};
+  bool valid = inb && qok;
+  if (valid) {
+    const double q0 = dets[3 * i], q1 = dets[3 * i + 1], q2 = dets[3 * i + 2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double t = (R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2) * scale;
+      if (!(fabs(t) < 1e8)) {
+        valid = false;
+      } else {
+        const double c = ceil(t - 0.5 * W);
+        l0[d] = (int)c;
+        frac[d] = (float)(t - c);
+      }
+    }
+  }
+  int mn[3], mx[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = valid ? l0[d] : 0x7fffffff;
+    mx[d] = valid ? l0[d] : -0x7fffffff;
+  }
+  block_minmax3(mn, mx, red);
+  const bool any = mn[0] <= mx[0];
+  const int e0 = mx[0] - mn[0] + W, e1 = mx[1] - mn[1] + W, e2 = mx[2] - mn[2] + W;
+  const bool use_lds = any && e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * e2 <= kCap;
+  const T *u = static_cast<const T *>(u_);
+  if (use_lds) {
+    // fine-grid index of every brick row/column, wrapped once per block
+    if (threadIdx.x < 64) {
+      const int t = threadIdx.x;
+      if (t < e0) wrap[0][t] = wrap_mod(mn[0] + t, nf);
+      if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t, nf);
+      if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
+    }
+    __syncthreads();
+    // rows of the brick: 8 rows at a time, 32 lanes along each row
+    const int lane32 = threadIdx.x & 31, rslot = threadIdx.x >> 5;
+    const int rows = e0 * e1;
+    for (int r = rslot; r < rows; r += kTile / 32) {
+      const int a = r / e1, b = r - a * e1;
+      const int64_t g = ((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf;
+      for (int c = lane32; c < e2; c += 32) brick[r * e2 + c] = u[g + wrap[2][c]];
+    }
+  }
+  float w0[W], w1[W], w2[W];
+  if (valid) {
+    es_weights<W>(frac[0], beta, w0);
+    es_weights<W>(frac[1], beta, w1);
+    es_weights<W>(frac[2], beta, w2);
+  }
+  if (use_lds) __syncthreads();
+  if (!inb) return;
+  const int64_t o = m * P + perm[i];
+  if (!valid) {
+    const float nan = __uint_as_float(0x7fc00000u);
+    if (CPLX) {
+      if (out_) static_cast<float2 *>(out_)[o] = make_float2(nan, nan);
+    } else {
+      if (out_) static_cast<float *>(out_)[o] = nan;
+      if (out_bf16) out_bf16[o] = 0x7fc0u;
+    }
+    return;
+  }
+  float sr = 0.f, si = 0.f;
+  if (use_lds) {
+    const int s0 = e1 * e2;
+    const int base = ((l0[0] - mn[0]) * e1 + (l0[1] - mn[1])) * e2 + (l0[2] - mn[2]);
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      float pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const T *row = brick + base + a * s0 + b * e2;
+        float rr = 0.f, ri = 0.f;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          if constexpr (CPLX) {
+            const float2 v = row[c];
+            rr = fmaf(w2[c], v.x, rr);
+            ri = fmaf(w2[c], v.y, ri);
+          } else {
+            rr = fmaf(w2[c], row[c], rr);
+          }
+        }
+        pr = fmaf(w1[b], rr, pr);
+        if (CPLX) pi = fmaf(w1[b], ri, pi);
+      }
+      sr = fmaf(w0[a], pr, sr);
+      if (CPLX) si = fmaf(w0[a], pi, si);
+    }
+  } else {
+    int g0[W], g1[W], g2[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      g0[a] = wrap_mod(l0[0] + a, nf);
+      g1[a] = wrap_mod(l0[1] + a, nf);
+      g2[a] = wrap_mod(l0[2] + a, nf);
+    }
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      float pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const T *row = u + ((int64_t)g0[a] * nf + g1[b]) * nf;
+        float rr = 0.f, ri = 0.f;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          if constexpr (CPLX) {
+            const float2 v = row[g2[c]];
+            rr = fmaf(w2[c], v.x, rr);
+            ri = fmaf(w2[c], v.y, ri);
+          } else {
+            rr = fmaf(w2[c], row[g2[c]], rr);
+          }
+        }
+        pr = fmaf(w1[b], rr, pr);
+        if (CPLX) pi = fmaf(w1[b], ri, pi);
+      }
+      sr = fmaf(w0[a], pr, sr);
+      if (CPLX) si = fmaf(w0[a], pi, si);
+    }
+  }
+  if (CPLX) {
+    if (out_) static_cast<float2 *>(out_)[o] = make_float2(sr, si);
+  } else {
+    if (out_) static_cast<float *>(out_)[o] = sr;
+    if (out_bf16) out_bf16[o] = f32_to_bf16(sr);
+  }
+}
+
 template <int W>
 static hipError_t interp_w(const Plan &pl, const float *quats, int64_t M, const float *detq,
                            int64_t P, void *out, uint16_t *out_bf16, hipStream_t s) {
+  const bool cplx = pl.domain == SPFEL_COMPLEX;
+  if (detq == nullptr) {
+    const int tiles = (int)((P + kTile - 1) / kTile);
+    const int64_t blocks = M * tiles;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (cplx)
+      hipLaunchKernelGGL((interp_tiled_kernel<W, true>), dim3((unsigned)blocks), dim3(kTile), 0, s,
+                         pl.u, pl.nf, (float)pl.beta, quats, M, pl.det_sorted, pl.det_perm, P,
+                         tiles, out, out_bf16);
+    else
+      hipLaunchKernelGGL((interp_tiled_kernel<W, false>), dim3((unsigned)blocks), dim3(kTile), 0,
+                         s, pl.u, pl.nf, (float)pl.beta, quats, M, pl.det_sorted, pl.det_perm, P,
+                         tiles, out, out_bf16);
+    return hipGetLastError();
+  }
   const int64_t total = M * P;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-  if (pl.domain == SPFEL_COMPLEX)
+  if (cplx)
     hipLaunchKernelGGL((interp_gather_kernel<W, true>), grid, block, 0, s, pl.u, pl.nf,
                        (float)pl.beta, quats, M, detq, P, out, out_bf16);
   else

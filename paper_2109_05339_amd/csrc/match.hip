@@ -26,10 +26,14 @@ constexpr int kGroup = 8;  // m-tiles per launch-order group
 // id is first remapped to make each XCD's blocks a contiguous range, and
 // that range is walked m-fastest in groups of kGroup m-tiles, so the blocks
 // resident on one XCD share slabs of S and D in that XCD's L2.
-__device__ inline void tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn) {
+__device__ inline void tile_of_block(int tiles_m, int tiles_n, int splits, int &tm, int &tn,
+                                     int &split) {
   const int G = gridDim.x, bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3, per = G >> 3, rem = G & 7;
-  const int v = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  int v = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  const int tiles = tiles_m * tiles_n;
+  split = v / tiles;
+  v -= split * tiles;
   const int gsize = kGroup * tiles_n;
   const int g = v / gsize;
   const int first = g * kGroup;
@@ -43,41 +47,51 @@ __device__ inline void tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
 constexpr int kBK = 32;         // floats of P per K step
 constexpr int kLdF = kBK + 4;   // LDS row stride (floats)
 
+// Four consecutive values X[r][k..k+3] of a row of length ld, zero beyond
+// row `rows` or column `kend` (kend <= ld).  vec: 16-byte aligned rows and
+// kend % 4 == 0, so a quad is either wholly inside or wholly outside.
 __device__ inline float4 load_row4(const float *__restrict__ X, int64_t rows, int64_t r,
-                                   int64_t P, int64_t k, bool vec) {
+                                   int64_t kend, int64_t k, bool vec, int64_t ld) {
   if (r >= rows) return make_float4(0.f, 0.f, 0.f, 0.f);
-  const float *p = X + r * P + k;
-  if (vec) return k < P ? *reinterpret_cast<const float4 *>(p) : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float *p = X + r * ld + k;
+  if (vec) return k < kend ? *reinterpret_cast<const float4 *>(p) : make_float4(0.f, 0.f, 0.f, 0.f);
   float4 v;
-  v.x = k < P ? p[0] : 0.f;
-  v.y = k + 1 < P ? p[1] : 0.f;
-  v.z = k + 2 < P ? p[2] : 0.f;
-  v.w = k + 3 < P ? p[3] : 0.f;
+  v.x = k < kend ? p[0] : 0.f;
+  v.y = k + 1 < kend ? p[1] : 0.f;
+  v.z = k + 2 < kend ? p[2] : 0.f;
+  v.w = k + 3 < kend ? p[3] : 0.f;
   return v;
 }
 
+// Split-K: block (split, tile) covers K range [split kchunk, (split+1)
+// kchunk).  Every split stores its partial tile; the last split of a tile
+// to arrive (per-tile counter) adds the partials in split order (a fixed
+// order, so results do not depend on arrival order) and runs the epilogue.
 __global__ __launch_bounds__(256, 2) void match_f32_kernel(
     const float *__restrict__ S, const float *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t m_offset,
-    unsigned long long *__restrict__ keys, int tiles_m, int tiles_n, int vec) {
+    unsigned long long *__restrict__ keys, int tiles_m, int tiles_n, int vec, int splits,
+    int64_t kchunk, float *__restrict__ partials, unsigned *__restrict__ counters) {
   __shared__ __attribute__((aligned(16))) float As[kBM * kLdF];
   __shared__ __attribute__((aligned(16))) float Bs[kBN * kLdF];
   __shared__ float sns[kBM], dns[kBN];
   __shared__ unsigned long long red[2][kBN];
 
-  int tm, tn;
-  tile_of_block(tiles_m, tiles_n, tm, tn);
+  int tm, tn, split;
+  tile_of_block(tiles_m, tiles_n, splits, tm, tn, split);
   const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = min(P, kbeg + kchunk);
 
   float4 ra[4], rb[4];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 4;
-      ra[i] = load_row4(S, M, row0 + r, P, k0 + c, vec);
-      rb[i] = load_row4(D, N, col0 + r, P, k0 + c, vec);
+      ra[i] = load_row4(S, M, row0 + r, kend, k0 + c, vec, P);
+      rb[i] = load_row4(D, N, col0 + r, kend, k0 + c, vec, P);
     }
   };
 
@@ -89,8 +103,8 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  gload(0);
-  for (int64_t k0 = 0; k0 < P; k0 += kBK) {
+  gload(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -99,7 +113,7 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
       *reinterpret_cast<float4 *>(&Bs[r * kLdF + c]) = rb[i];
     }
     __syncthreads();
-    if (k0 + kBK < P) gload(k0 + kBK);
+    if (k0 + kBK < kend) gload(k0 + kBK);
     // Fresh partial sums per K step keep every accumulation chain short:
     // at most 2 kBK roundings inside the step plus one per step.
     floatx16 part[2][2];
@@ -134,6 +148,47 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
       for (int j = 0; j < 2; ++j) acc[i][j] += part[i][j];
   }
 
+  if (splits > 1) {
+    // publish this split's partial tile, then let the last arrival finish
+    const int tile = tm * tiles_n + tn;
+    float *mine = partials + ((int64_t)tile * splits + split) * (kBM * kBN);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mine[((i * 2 + j) * 16 + r) * 256 + tid] = acc[i][j][r];
+    __threadfence();
+    __shared__ unsigned arrived;
+    __syncthreads();
+    if (tid == 0) arrived = atomicAdd(counters + tile, 1u);
+    __syncthreads();
+    if (arrived != (unsigned)(splits - 1)) return;
+    __threadfence();
+    floatx16 sum[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sum[i][j][r] = 0.f;
+    for (int sp = 0; sp < splits; ++sp) {
+      const float *part = partials + ((int64_t)tile * splits + sp) * (kBM * kBN);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            sum[i][j][r] += sp == split ? acc[i][j][r]
+                                        : __builtin_nontemporal_load(&part[((i * 2 + j) * 16 + r) * 256 + tid]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = sum[i][j];
+    if (tid == 0) counters[tile] = 0u;  // ready for the next launch
+  }
   if (tid < kBM) {
     sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
   } else {
@@ -203,15 +258,70 @@ hipError_t launch_unpack_keys(const unsigned long long *keys, int32_t *idx, floa
 
 static bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Resident blocks of match_f32_kernel on the whole chip (256 CUs x 2).
+constexpr int kF32Slots = 512;
+
+// Number of K splits that best fills the chip's last round of blocks, with
+// each split at least 1024 values of P long.  Launches of four or more full
+// rounds lose little to their last round and are not split.
+int match_f32_splits(int64_t M, int64_t N, int64_t P) {
+  const int64_t tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+  if (tiles >= 4 * kF32Slots) return 1;
+  int best = 1;
+  double best_eff = 0.0;
+  for (int s = 1; s <= 4; ++s) {
+    if (s > 1 && P / s < 1024) break;
+    const int64_t units = tiles * s;
+    const int64_t rounds = (units + kF32Slots - 1) / kF32Slots;
+    const double eff = (double)units / (double)(rounds * kF32Slots);
+    if (eff > best_eff + 0.02) {
+      best_eff = eff;
+      best = s;
+    }
+  }
+  return best;
+}
+
+size_t match_f32_workspace_bytes(int64_t M, int64_t N, int64_t P) {
+  const int64_t tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+  const int s = match_f32_splits(M, N, P);
+  size_t b = (size_t)N * sizeof(unsigned long long);
+  b = (b + 255) & ~(size_t)255;
+  if (s > 1) {
+    b += (size_t)tiles * sizeof(unsigned);
+    b = (b + 255) & ~(size_t)255;
+    b += (size_t)tiles * s * kBM * kBN * sizeof(float);
+  }
+  return b;
+}
+
 hipError_t launch_match_f32(const float *S, const float *D, const float *sn, const float *dn,
-                            int64_t M, int64_t N, int64_t P, int64_t m_offset,
-                            unsigned long long *keys, hipStream_t s) {
+                            int64_t M, int64_t N, int64_t P, int64_t m_offset, void *workspace,
+                            hipStream_t s) {
   const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
-  const int64_t blocks = (int64_t)tiles_m * tiles_n;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  const int splits = match_f32_splits(M, N, P);
+  const int64_t blocks = tiles * splits;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  // K chunk: a multiple of the K step (and of 4 for the vector loads)
+  int64_t kchunk = (P + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
   const int vec = (P % 4 == 0) && al16(S) && al16(D);
+  char *ws = static_cast<char *>(workspace);
+  auto *keys = reinterpret_cast<unsigned long long *>(ws);
+  size_t off = ((size_t)N * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  unsigned *counters = nullptr;
+  float *partials = nullptr;
+  if (splits > 1) {
+    counters = reinterpret_cast<unsigned *>(ws + off);
+    off = (off + (size_t)tiles * sizeof(unsigned) + 255) & ~(size_t)255;
+    partials = reinterpret_cast<float *>(ws + off);
+    hipError_t e = launch_fill_zero(counters, (size_t)tiles * sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(match_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M, N,
-                     P, (uint32_t)m_offset, keys, tiles_m, tiles_n, vec);
+                     P, (uint32_t)m_offset, keys, tiles_m, tiles_n, vec, splits, kchunk, partials,
+                     counters);
   return hipGetLastError();
 }
 
@@ -264,8 +374,8 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
   __shared__ float sns[kBM], dns[kBN];
   __shared__ uint32_t red[2][kBN][8];
 
-  int tm, tn;
-  tile_of_block(tiles_m, tiles_n, tm, tn);
+  int tm, tn, split;
+  tile_of_block(tiles_m, tiles_n, 1, tm, tn, split);
   const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;

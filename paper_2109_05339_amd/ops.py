@@ -86,21 +86,42 @@ class Plan:
         except Exception:
             pass
 
+    def set_detector(self, det_q: torch.Tensor) -> None:
+        """Register the detector template (P, 3); later ``slice`` and
+        ``merge_adjoint`` calls without ``det_q`` use its tiled kernels."""
+        _need(det_q, "det_q", torch.float32, self.device)
+        if det_q.dim() != 2 or det_q.shape[1] != 3:
+            raise ValueError("det_q must be (P, 3)")
+        check(_lib.lib().spfel_set_detector(self._h, _p(det_q), det_q.shape[0],
+                                            _stream(self.device)))
+        self.n_det_points = det_q.shape[0]
+
+    def _detector(self, det_q):
+        if det_q is None:
+            P = getattr(self, "n_det_points", 0)
+            if P == 0:
+                raise ValueError("no det_q given and no detector registered")
+            return None, P
+        _need(det_q, "det_q", torch.float32, self.device)
+        if det_q.dim() != 2 or det_q.shape[1] != 3:
+            raise ValueError("det_q must be (P, 3)")
+        return det_q, det_q.shape[0]
+
     def set_model(self, model: torch.Tensor) -> None:
         N = self.n_model
         _need(model, "model", self.cdtype, self.device, (N, N, N))
         check(_lib.lib().spfel_set_model(self._h, _p(model), _stream(self.device)))
 
-    def slice(self, quats: torch.Tensor, det_q: torch.Tensor, out: bool = True,
+    def slice(self, quats: torch.Tensor, det_q: Optional[torch.Tensor] = None, out: bool = True,
               bf16: bool = False, norms: bool = False):
         """Model images at orientations ``quats`` (M,4) and detector points
-        ``det_q`` (P,3).  Returns (slices or None, bf16 copy or None,
-        squared norms or None)."""
+        ``det_q`` (P,3) (None: the registered detector).  Returns (slices or
+        None, bf16 copy or None, squared norms or None)."""
         _need(quats, "quats", torch.float32, self.device)
-        _need(det_q, "det_q", torch.float32, self.device)
-        if quats.dim() != 2 or quats.shape[1] != 4 or det_q.dim() != 2 or det_q.shape[1] != 3:
-            raise ValueError("quats must be (M, 4) and det_q (P, 3)")
-        M, P = quats.shape[0], det_q.shape[0]
+        if quats.dim() != 2 or quats.shape[1] != 4:
+            raise ValueError("quats must be (M, 4)")
+        det_q, P = self._detector(det_q)
+        M = quats.shape[0]
         s = torch.empty((M, P), dtype=self.cdtype, device=self.device) if out else None
         sb = torch.empty((M, P), dtype=torch.bfloat16, device=self.device) if bf16 else None
         sn = torch.empty((M,), dtype=torch.float32, device=self.device) if norms else None
@@ -108,14 +129,15 @@ class Plan:
                                      _stream(self.device)))
         return s, sb, sn
 
-    def merge_adjoint(self, quats: torch.Tensor, det_q: torch.Tensor, values: torch.Tensor,
-                      weights: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-                      flags: int = 0) -> Optional[torch.Tensor]:
+    def merge_adjoint(self, quats: torch.Tensor, det_q: Optional[torch.Tensor],
+                      values: torch.Tensor, weights: Optional[torch.Tensor] = None,
+                      out: Optional[torch.Tensor] = None, flags: int = 0) -> Optional[torch.Tensor]:
         """Type-1 adjoint of the values (n_img, P) at the images' points,
-        onto N^3 modes.  With MERGE_DEFER only spreads (returns None)."""
+        onto N^3 modes (det_q None: the registered detector).  With
+        MERGE_DEFER only spreads (returns None)."""
         _need(quats, "quats", torch.float32, self.device)
-        _need(det_q, "det_q", torch.float32, self.device)
-        n_img, P = quats.shape[0], det_q.shape[0]
+        det_q, P = self._detector(det_q)
+        n_img = quats.shape[0]
         _need(values, "values", self.cdtype, self.device, (n_img, P))
         if weights is not None:
             _need(weights, "weights", torch.float32, self.device, (n_img, P))

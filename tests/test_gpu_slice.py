@@ -153,3 +153,53 @@ def test_state_and_argument_errors():
     plan.close()
     with pytest.raises(spfel.SpfelStateError):
         plan.slice(q, det)
+
+
+@pytest.mark.parametrize("domain", [spfel.REAL, spfel.COMPLEX])
+def test_registered_detector_tiles_are_bitwise_equal_to_generic_path(domain):
+    """The tiled LDS-brick kernel reads the same fine-grid values with the
+    same weights in the same order as the per-point gather."""
+    cfg = synth.config(1)
+    det = detector(cfg.n_det)
+    q = synth.quaternions(cfg, "ref_quats", 40)
+    plan = make_plan(cfg.n_model, domain)
+    if domain == spfel.REAL:
+        plan.set_model(gpu(model(1)))
+    else:
+        plan.set_model(gpu(synth.complex_perturbation(synth.config(4), model(1)), torch.complex64))
+    plan.set_detector(gpu(det))
+    a, ab, an = plan.slice(gpu(q), None, bf16=domain == spfel.REAL, norms=True)
+    b, bb, bn = plan.slice(gpu(q), gpu(det), bf16=domain == spfel.REAL, norms=True)
+    np.testing.assert_array_equal(host(a), host(b))
+    np.testing.assert_array_equal(host(an), host(bn))
+    if domain == spfel.REAL:
+        np.testing.assert_array_equal(host(ab.view(torch.int16)), host(bb.view(torch.int16)))
+
+
+@pytest.mark.parametrize("cid,rows", [(2, 4), (5, 2)])
+def test_registered_detector_large_shapes_against_oracle(cid, rows):
+    cfg = synth.config(cid)
+    det = detector(cfg.n_det)
+    q = synth.quaternions(cfg, "image_quats", rows)
+    plan = make_plan(cfg.n_model)
+    plan.set_model(gpu(model(cid)))
+    plan.set_detector(gpu(det))
+    s = host(plan.slice(gpu(q))[0])
+    assert rel(s, oracle_slices(model(cid), q, det, real=True)) <= TOL
+
+
+def test_registered_scattered_points_use_the_global_fallback():
+    """Points spread over the whole cube make every tile's brick exceed the
+    LDS budget; the block then gathers from global memory, same values."""
+    N = 33
+    det = np.concatenate([synth.random_points(21, 700), synth.detector_q(16)])
+    q = synth.quaternions(synth.config(1), "ref_quats", 6)
+    plan = make_plan(N)
+    plan.set_model(gpu(model(1)))
+    plan.set_detector(gpu(det))
+    a = host(plan.slice(gpu(q))[0])
+    b = host(plan.slice(gpu(q), gpu(det))[0])
+    np.testing.assert_array_equal(a, b)
+    assert rel(a, oracle_slices(model(1), q, det, real=True)) <= TOL
+    with pytest.raises(ValueError):
+        make_plan(N).slice(gpu(q))

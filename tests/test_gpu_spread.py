@@ -95,3 +95,44 @@ def test_defer_and_accumulate_flags():
     empty = host(plan.merge_adjoint(torch.zeros((0, 4), device=DEV), gpu(det),
                                     torch.zeros((0, det.shape[0]), device=DEV)))
     assert np.all(empty == 0)
+
+
+@pytest.mark.parametrize("domain", [spfel.REAL, spfel.COMPLEX])
+def test_registered_detector_spread_against_oracle(domain):
+    cfg = synth.config(1)
+    det = detector(cfg.n_det)
+    q = synth.quaternions(cfg, "image_quats", 30)
+    g = np.random.default_rng(6)
+    plan = spfel.Plan(cfg.n_model, domain=domain, device=DEV)
+    plan.set_detector(gpu(det))
+    w = synth.pixel_weights(cfg, 30, det.shape[0])
+    if domain == spfel.REAL:
+        y = g.poisson(20.0, (30, det.shape[0])).astype(np.float32)
+        yt = gpu(y)
+    else:
+        y = (g.standard_normal((30, det.shape[0])) + 1j * g.standard_normal((30, det.shape[0]))).astype(np.complex64)
+        yt = gpu(y, torch.complex64)
+    out = host(plan.merge_adjoint(gpu(q), None, yt, gpu(w)))
+    ref = oracle_merge(y.astype(np.complex128) if domain else y, q, det, cfg.n_model, domain == spfel.REAL, w)
+    assert rel(out, ref) <= TOL
+    gen = host(plan.merge_adjoint(gpu(q), gpu(det), yt, gpu(w)))
+    assert rel(out, gen) <= 1e-6
+
+
+def test_registered_detector_spread_c4_shape_and_fallback():
+    cfg = synth.config(4)
+    det = detector(cfg.n_det)
+    q = synth.quaternions(cfg, "image_quats", 12)
+    g = np.random.default_rng(8)
+    y = (g.standard_normal((12, det.shape[0])) + 1j * g.standard_normal((12, det.shape[0]))).astype(np.complex64)
+    plan = spfel.Plan(cfg.n_model, domain=spfel.COMPLEX, device=DEV)
+    plan.set_detector(gpu(det))
+    out = host(plan.merge_adjoint(gpu(q), None, gpu(y, torch.complex64)))
+    assert rel(out, oracle_merge(y.astype(np.complex128), q, det, cfg.n_model, False)) <= TOL
+    scat = synth.random_points(22, 600)
+    plan2 = spfel.Plan(13, device=DEV)
+    plan2.set_detector(gpu(scat))
+    yr = g.standard_normal((3, 600)).astype(np.float32)
+    q3 = synth.quaternions(cfg, "ref_quats", 3)
+    out2 = host(plan2.merge_adjoint(gpu(q3), None, gpu(yr)))
+    assert rel(out2, oracle_merge(yr, q3, scat, 13, True)) <= TOL
