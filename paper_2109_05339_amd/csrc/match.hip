@@ -358,8 +358,16 @@ __device__ inline void insert8(unsigned long long (&top)[8], unsigned long long 
   }
 }
 
+// The large-tile kernel is used when its 256 x 256 tiles fill at least four
+// rounds of the chip's 256 resident blocks; otherwise 128 x 128 tiles.
+int match_bf16_tile_rows(int64_t M, int64_t N) {
+  const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
+  return big >= 4 * 256 ? 256 : 128;
+}
+
 size_t match_bf16_candidate_bytes(int64_t M, int64_t N) {
-  const int64_t tiles_m = (M + kBM - 1) / kBM;
+  const int64_t tr = match_bf16_tile_rows(M, N);
+  const int64_t tiles_m = (M + tr - 1) / tr;
   return (size_t)tiles_m * (size_t)N * 8 * sizeof(uint32_t);
 }
 
@@ -472,13 +480,143 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
   }
 }
 
+// Large-tile form for launches with many tiles: 256 x 256 tiles, each of
+// the 4 wavefronts owning a 128 x 128 quarter (16 MFMA accumulators, which
+// cuts LDS reads per MFMA in half against 64 x 64 quarters), A and B staged
+// in a double-buffered LDS ring with one barrier per K step.
+constexpr int kBM2 = 256, kBN2 = 256, kBK2 = 64, kLd2 = kBK2 + 8;
+constexpr int kStage2 = (kBM2 + kBN2) * kLd2;   // bf16 values per LDS stage
+
+__global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
+    const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
+    const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
+    int tiles_m, int tiles_n, int vec) {
+  __shared__ __attribute__((aligned(16))) uint16_t smem[2 * kStage2];
+
+  int tm, tn, split;
+  tile_of_block(tiles_m, tiles_n, 1, tm, tn, split);
+  const int64_t row0 = (int64_t)tm * kBM2, col0 = (int64_t)tn * kBN2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+
+  uint4 ra[8], rb[8];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+      ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
+      rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
+    }
+  };
+  auto lstore = [&](int buf) {
+    uint16_t *As = smem + buf * kStage2;
+    uint16_t *Bs = As + kBM2 * kLd2;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+      *reinterpret_cast<uint4 *>(&As[r * kLd2 + c]) = ra[i];
+      *reinterpret_cast<uint4 *>(&Bs[r * kLd2 + c]) = rb[i];
+    }
+  };
+
+  floatx16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int64_t steps = (P + kBK2 - 1) / kBK2;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t st = 0; st < steps; ++st) {
+    const int buf = (int)(st & 1);
+    if (st + 1 < steps) gload((st + 1) * kBK2);
+    const uint16_t *As = smem + buf * kStage2;
+    const uint16_t *Bs = As + kBM2 * kLd2;
+#pragma unroll
+    for (int kk = 0; kk < kBK2 / 16; ++kk) {
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 128 + i * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 128 + j * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (st + 1 < steps) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue (LDS reused): norms of the tile's rows and columns, then each
+  // column's 8 smallest proxies; candidate words carry the row in 8 bits.
+  float *sns = reinterpret_cast<float *>(smem);
+  float *dns = sns + kBM2;
+  uint32_t *red = reinterpret_cast<uint32_t *>(dns + kBN2);   // [2][kBN2][8]
+  sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
+  dns[tid] = col0 + tid < N ? dn[col0 + tid] : 0.f;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cl = wn * 128 + j * 32 + lr;
+    uint32_t top[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) top[q] = ~0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rl = wm * 128 + i * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+        if (row0 + rl < M) {
+          const float b = fmaf(-2.0f, acc[i][j][r], sns[rl] + dns[cl]);
+          insert8(top, (float_key(b) & ~255u) | (uint32_t)rl);
+        }
+      }
+    uint32_t other[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) other[q] = __shfl_xor(top[q], 32);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) insert8(top, other[q]);
+    if (lh == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[(wm * kBN2 + cl) * 8 + q] = top[q];
+    }
+  }
+  __syncthreads();
+  if (col0 + tid < N) {
+    uint32_t top[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) top[q] = red[tid * 8 + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) insert8(top, red[(kBN2 + tid) * 8 + q]);
+    uint4 *dst = reinterpret_cast<uint4 *>(cand + ((int64_t)tm * N + col0 + tid) * 8);
+    dst[0] = make_uint4(top[0], top[1], top[2], top[3]);
+    dst[1] = make_uint4(top[4], top[5], top[6], top[7]);
+  }
+}
+
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *sn,
                              const float *dn, int64_t M, int64_t N, int64_t P, uint32_t *cand,
                              hipStream_t s) {
+  const int vec = (P % 8 == 0) && al16(S) && al16(D);
+  if (match_bf16_tile_rows(M, N) == 256) {
+    const int tiles_m = (int)((M + kBM2 - 1) / kBM2), tiles_n = (int)((N + kBN2 - 1) / kBN2);
+    const int64_t blocks = (int64_t)tiles_m * tiles_n;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(match_bf16_big_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn,
+                       dn, M, N, P, cand, tiles_m, tiles_n, vec);
+    return hipGetLastError();
+  }
   const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
   const int64_t blocks = (int64_t)tiles_m * tiles_n;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const int vec = (P % 8 == 0) && al16(S) && al16(D);
   hipLaunchKernelGGL(match_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
                      N, P, cand, tiles_m, tiles_n, vec);
   return hipGetLastError();
@@ -489,7 +627,8 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
 // float32 against the float32 slices and image, and fold the best into the
 // caller's running (best_dist, best_idx).
 __global__ __launch_bounds__(256) void rescore_kernel(
-    const uint32_t *__restrict__ cand, int tiles_m, int64_t N, int64_t P, uint32_t m_offset,
+    const uint32_t *__restrict__ cand, int tiles_m, int tile_rows, int64_t N, int64_t P,
+    uint32_t m_offset,
     const float *__restrict__ S32, const float *__restrict__ D32, const float *__restrict__ sn,
     const float *__restrict__ dn, int32_t *__restrict__ best_idx, float *__restrict__ best_dist,
     int vec) {
@@ -504,8 +643,9 @@ __global__ __launch_bounds__(256) void rescore_kernel(
     const int t = c >> 3, s = c & 7;
     const uint32_t k = cand[((int64_t)t * N + n) * 8 + s];
     if (k != ~0u) {
-      const uint32_t m = (uint32_t)t * kBM + (k & 127u);
-      insert8(top, ((unsigned long long)(k & ~127u) << 32) | m);
+      const uint32_t low = (uint32_t)tile_rows - 1u;
+      const uint32_t m = (uint32_t)t * (uint32_t)tile_rows + (k & low);
+      insert8(top, ((unsigned long long)(k & ~low) << 32) | m);
     }
   }
 #pragma unroll
@@ -575,10 +715,11 @@ __global__ __launch_bounds__(256) void rescore_kernel(
 hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N, int64_t P, int64_t m_offset,
                           const float *S32, const float *D32, const float *sn, const float *dn,
                           int32_t *best_idx, float *best_dist, hipStream_t s) {
-  const int tiles_m = (int)((M + kBM - 1) / kBM);
+  const int tr = match_bf16_tile_rows(M, N);
+  const int tiles_m = (int)((M + tr - 1) / tr);
   const int vec = (P % 4 == 0) && al16(S32) && al16(D32);
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, cand, tiles_m,
-                     N, P, (uint32_t)m_offset, S32, D32, sn, dn, best_idx, best_dist, vec);
+                     tr, N, P, (uint32_t)m_offset, S32, D32, sn, dn, best_idx, best_dist, vec);
   return hipGetLastError();
 }
 

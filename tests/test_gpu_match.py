@@ -187,3 +187,31 @@ def test_bf16_chunked_streaming():
     assert np.all(a[0][ok] == m1[ok]) and np.all(b[0][ok] == m1[ok])
     # chunked never does worse than one-shot in exact distance
     assert np.all(ex[b[0], cols] <= ex[a[0], cols] + E[b[0], cols] + E[a[0], cols])
+
+
+def test_bf16_large_tile_kernel_against_oracle_on_sampled_images():
+    """8,192 x 8,192 fills >= 4 rounds of 256 x 256 tiles (large-tile BF16
+    kernel); a ragged P of 136 exercises the scalar loads.  The oracle
+    checks 192 sampled images exactly."""
+    g = np.random.default_rng(11)
+    M, N, P = 8192, 8192, 136
+    base = g.gamma(2.0, 10.0, (M, P)).astype(np.float32)
+    pick = g.integers(0, M, N)
+    D = g.poisson(base[pick]).astype(np.float32)
+    assert spfel.match_workspace_bytes(M, N, P, spfel.MATCH_BF16_RESCORE8) == (M // 256) * N * 32
+    ib, db = run_bf16(base, D)
+    cols = np.sort(g.choice(N, 192, replace=False))
+    S64, Ds = base.astype(np.float64), D[cols].astype(np.float64)
+    ex = om.distances_expanded(S64, Ds)
+    absdot = np.abs(S64) @ np.abs(Ds).T
+    E = om.fp32_distance_bound((S64 ** 2).sum(1)[:, None], (Ds ** 2).sum(1)[None, :], absdot, chain_fp32(P))
+    order = np.argsort(ex, axis=0, kind="stable")
+    c = np.arange(len(cols))
+    m1, m2 = order[0], order[1]
+    decided = ex[m2, c] - ex[m1, c] > E[m1, c] + E[m2, c]
+    b16 = (S64 ** 2).sum(1)[:, None] + (Ds ** 2).sum(1)[None, :] - 2 * (om.bf16_round(base).astype(np.float64) @ Ds.T)
+    top8 = om.topk(b16, 8)
+    ok = decided & np.array([m1[n] in top8[:, n] for n in c])
+    assert ok.mean() >= 0.9
+    np.testing.assert_array_equal(ib[cols][ok], m1[ok])
+    assert np.all(np.abs(db[cols] - ex[ib[cols], c]) <= 2 * E[ib[cols], c])
