@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip BF16 and spread side runs")
     ap.add_argument("--cpu-sample", type=int, default=200, help="orientations in the oracle sample")
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection run: one step of each path and a plain 1 GiB "
+                         "device copy (the copy calibrates FETCH_SIZE/WRITE_SIZE), no timing")
     return ap.parse_args()
 
 
@@ -133,6 +136,18 @@ def main() -> int:
         match_ms = float(np.mean([c.elapsed_time(d) for _, _, c, d in marks]))
         step_ms = float(np.mean([a.elapsed_time(d) for a, _, _, d in marks]))
         return wall * 1e3, step_ms, slice_ms, match_ms
+
+    if args.counters:
+        step_fp32()
+        step_bf16()
+        plan.merge_adjoint(ref_q[:n_img].contiguous(), None, images)
+        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("counter run done: one fp32 step, one bf16 step, one merge, one 1 GiB copy")
+        print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 4}), flush=True)
+        return 0
 
     log(f"timing fp32 path: {args.warmup} warmup + {args.steps} steps")
     wall_ms, step_ms, slice_ms, match_ms = timed(step_fp32, args.steps, args.warmup)

@@ -91,7 +91,8 @@ int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes);
 /* Register the detector template (section II-A: the model images are
  * computed on a predetermined geometry; section IV-A: one flat detector).
  * det_q: P x 3 float32 device points.  The plan keeps a copy sorted along a
- * 3D Morton curve, so runs of 256 consecutive points are compact patches,
+ * Hilbert curve on the points' principal plane, so runs of 256 consecutive
+ * points are compact patches,
  * and spfel_slice / spfel_merge_adjoint called with det_q = NULL (and the
  * same P) use it: each (orientation, patch) then stages its fine-grid brick
  * in LDS.  Outputs stay in the caller's pixel order.  This call copies the

@@ -77,6 +77,66 @@ void kernel_transform(int N, int nf, int w, double beta, double *out) {
   }
 }
 
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi
+// rotations: columns of V are the eigenvectors, ev the eigenvalues.
+static void sym3_eigen(const double A_in[3][3], double V[3][3], double ev[3]) {
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      A[i][j] = A_in[i][j];
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    if (off < 1e-30 * (A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2]) || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double theta = 0.5 * (A[q][q] - A[p][p]) / A[p][q];
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) ev[i] = A[i][i];
+}
+
+// Position of lattice cell (x, y) along the Hilbert curve filling an n x n
+// lattice (n a power of two): descend the quadrants from the largest,
+// adding each quadrant's offset and reflecting/transposing the coordinates
+// into the sub-curve's frame.
+static uint64_t hilbert_index(uint32_t n, uint32_t x, uint32_t y) {
+  uint64_t d = 0;
+  for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - (x & (s - 1));
+        y = s - 1 - (y & (s - 1));
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
 static std::mutex g_mu;
 static std::set<Plan *> g_live;
 
@@ -261,41 +321,54 @@ int spfel_set_detector(spfel_plan plan, const float *det_q, int64_t P, void *str
   hipError_t e = hipMemcpyAsync(h.data(), det_q, h.size() * sizeof(float), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "set_detector: copy to host");
-  // 3D Morton key of each point on a 1024^3 lattice over the points' box;
-  // non-finite points sort last.
-  float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
-  for (int64_t i = 0; i < P; ++i)
-    for (int d = 0; d < 3; ++d) {
-      const float v = h[3 * i + d];
-      if (std::isfinite(v)) {
-        lo[d] = std::min(lo[d], v);
-        hi[d] = std::max(hi[d], v);
-      }
+  // Order the points along a Hilbert curve on their principal plane (the
+  // detector template is a 2D surface): consecutive points are neighbours,
+  // so each run of kTile points is a compact patch.  Non-finite points last.
+  double mean[3] = {0, 0, 0};
+  int64_t nfin = 0;
+  std::vector<char> fin((size_t)P);
+  for (int64_t i = 0; i < P; ++i) {
+    fin[i] = std::isfinite(h[3 * i]) && std::isfinite(h[3 * i + 1]) && std::isfinite(h[3 * i + 2]);
+    if (!fin[i]) continue;
+    for (int d = 0; d < 3; ++d) mean[d] += h[3 * i + d];
+    ++nfin;
+  }
+  for (int d = 0; d < 3; ++d) mean[d] /= (nfin > 0 ? (double)nfin : 1.0);
+  double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int64_t i = 0; i < P; ++i) {
+    if (!fin[i]) continue;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) C[a][b] += (h[3 * i + a] - mean[a]) * (h[3 * i + b] - mean[b]);
+  }
+  double V[3][3], ev[3];
+  sym3_eigen(C, V, ev);
+  int order[3] = {0, 1, 2};
+  std::sort(order, order + 3, [&](int a, int b) { return ev[a] > ev[b]; });
+  std::vector<double> uv((size_t)P * 2, 0.0);
+  double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+  for (int64_t i = 0; i < P; ++i) {
+    if (!fin[i]) continue;
+    for (int k = 0; k < 2; ++k) {
+      double v = 0.0;
+      for (int d = 0; d < 3; ++d) v += (h[3 * i + d] - mean[d]) * V[d][order[k]];
+      uv[2 * i + k] = v;
+      lo[k] = std::min(lo[k], v);
+      hi[k] = std::max(hi[k], v);
     }
-  auto spread_bits = [](uint32_t v) {
-    uint64_t x = v & 0x3ff;
-    x = (x | (x << 16)) & 0x030000FF;
-    x = (x | (x << 8)) & 0x0300F00F;
-    x = (x | (x << 4)) & 0x030C30C3;
-    x = (x | (x << 2)) & 0x09249249;
-    return x;
-  };
+  }
+  // lattice of about twice the point spacing's resolution, a power of two
+  int res = 1;
+  while ((double)res * (double)res < 4.0 * (double)P && res < (1 << 15)) res <<= 1;
+  const double span = std::max(std::max(hi[0] - lo[0], hi[1] - lo[1]), 1e-300);
   std::vector<uint64_t> key((size_t)P);
   for (int64_t i = 0; i < P; ++i) {
-    uint64_t k = 0;
-    bool fin = true;
-    for (int d = 0; d < 3; ++d) {
-      const float v = h[3 * i + d];
-      if (!std::isfinite(v)) {
-        fin = false;
-        break;
-      }
-      const float span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0f;
-      int qv = (int)((v - lo[d]) / span * 1023.0f + 0.5f);
-      qv = std::min(std::max(qv, 0), 1023);
-      k |= spread_bits((uint32_t)qv) << d;
+    if (!fin[i]) {
+      key[i] = ~0ull;
+      continue;
     }
-    key[i] = fin ? k : ~0ull;
+    uint32_t gx = (uint32_t)std::min(std::max((uv[2 * i] - lo[0]) / span * (res - 1) + 0.5, 0.0), (double)(res - 1));
+    uint32_t gy = (uint32_t)std::min(std::max((uv[2 * i + 1] - lo[1]) / span * (res - 1) + 0.5, 0.0), (double)(res - 1));
+    key[i] = hilbert_index((uint32_t)res, gx, gy);
   }
   std::vector<int32_t> perm((size_t)P);
   std::iota(perm.begin(), perm.end(), 0);

@@ -36,8 +36,9 @@ struct Plan {
   // Per-block partial sums of the weighted-residual loss.
   double *partials = nullptr;
   // Registered detector template (spfel_set_detector): points sorted along
-  // a 3D Morton curve so that every run of kTile consecutive points is a
-  // compact patch; det_perm maps a sorted position to the caller's pixel.
+  // a Hilbert curve on their principal plane so that every run of kTile
+  // consecutive points is a compact patch; det_perm maps a sorted position
+  // to the caller's pixel.
   float *det_sorted = nullptr;   // det_P x 3
   int32_t *det_perm = nullptr;   // det_P
   int64_t det_P = 0;

@@ -106,13 +106,16 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
 
 // ---------------------------------------------------------------------------
 // Tiled interpolation over the registered detector.  One block of kTile
-// threads takes one orientation and one detector tile (kTile Morton-sorted,
-// hence spatially compact, template points): the rotated points' support
+// threads takes one orientation and one detector tile (kTile consecutive
+// points of the Hilbert-ordered template, hence a compact patch): the rotated points' support
 // cells span a small axis-aligned brick of the fine grid, which the block
 // stages in LDS with coalesced row reads; the w^3 gather then reads LDS
 // instead of L1/L2.  A brick larger than the LDS budget (possible only for
 // unusually spread tiles) makes the block gather from global memory.
-constexpr int kBrickBytes = 32768;
+// LDS budget of a brick: 32 KB of float (4 blocks per CU) or 64 KB of
+// float2 cells.
+template <bool CPLX>
+constexpr int brick_bytes() { return CPLX ? 65536 : 32768; }
 
 __device__ inline int wrap_mod(int v, int n) {
   v %= n;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kTile) void interp_tiled_kernel(
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     void *__restrict__ out_, uint16_t *__restrict__ out_bf16) {
   typedef typename std::conditional<CPLX, float2, float>::type T;
-  constexpr int kCap = kBrickBytes / (int)sizeof(T);
+  constexpr int kCap = brick_bytes<CPLX>() / (int)sizeof(T);
   __shared__ __attribute__((aligned(16))) T brick[kCap];
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];

@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void spread_atomic_kernel(
 // LDS brick with LDS atomics, and the brick is then added to the fine grid
 // with one global atomic per nonzero cell (instead of w^3 per point).  A
 // brick beyond the LDS budget falls back to per-point global atomics.
-constexpr int kSpreadBrickBytes = 32768;
+template <bool CPLX>
+constexpr int spread_brick_bytes() { return CPLX ? 65536 : 32768; }
 
 __device__ inline int wrap_mod_s(int v, int n) {
   v %= n;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kTile) void spread_tiled_kernel(
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     const void *__restrict__ values_, const float *__restrict__ weights) {
   constexpr int kComp = CPLX ? 2 : 1;
-  constexpr int kCap = kSpreadBrickBytes / (4 * kComp);
+  constexpr int kCap = spread_brick_bytes<CPLX>() / (4 * kComp);
   __shared__ __attribute__((aligned(16))) float brick[kCap * kComp];
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];

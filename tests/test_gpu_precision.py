@@ -1,0 +1,60 @@
+"""Precision form at full size (workload 3: 33^3 model, 64x64 detector,
+50,000 references, 2,048 images): the BF16 distance GEMM with per-image
+top-8 FP32 rescoring against the FP32 matcher on the same GPU and against
+float64 distances on a 512-image subset."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2109_05339_amd as spfel
+from oracle import match as om
+from tests._common import DEV, gpu, host, model, detector
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c3_bf16_rescore_against_fp32_and_fp64():
+    cfg = synth.config(3)
+    M, n_img, P = cfg.n_refs, cfg.n_images, cfg.n_pix
+    plan = spfel.Plan(cfg.n_model, device=DEV)
+    plan.set_detector(gpu(detector(cfg.n_det)))
+    plan.set_model(gpu(model(3)))
+    lam0 = plan.slice(gpu(synth.quaternions(cfg, "image_quats", n_img)))[0].clamp_(min=0)
+    alpha = synth.photon_scale(host(lam0), cfg.photons)
+    images = gpu(synth.poisson_counts(cfg, alpha * host(lam0)))
+    plan.set_model(gpu(alpha * model(3)))
+    S, Sb, sn = plan.slice(gpu(synth.quaternions(cfg, "ref_quats", M)), bf16=True, norms=True)
+    dn = spfel.row_norm2(images)
+    i32, d32 = spfel.new_best(n_img, DEV)
+    spfel.match(S, sn, images, dn, i32, d32)
+    ib, db = spfel.new_best(n_img, DEV)
+    spfel.match(Sb, sn, images.to(torch.bfloat16), dn, ib, db, mode=spfel.MATCH_BF16_RESCORE8,
+                slices_f32=S, images_f32=images)
+    i32, ib, db = host(i32), host(ib), host(db)
+    agree = np.mean(i32 == ib)
+    # float64 distances of the same float32 values on the first 512 images
+    S64 = host(S).astype(np.float64)
+    D64 = host(images[:512]).astype(np.float64)
+    ex = om.distances_expanded(S64, D64)
+    absdot = np.abs(S64) @ np.abs(D64).T
+    L = 36 + P // 32
+    E = om.fp32_distance_bound((S64 ** 2).sum(1)[:, None], (D64 ** 2).sum(1)[None, :], absdot, L)
+    c = np.arange(512)
+    order = np.argpartition(ex, 1, axis=0)[:2]
+    first = np.where(ex[order[0], c] <= ex[order[1], c], order[0], order[1])
+    second = np.where(ex[order[0], c] <= ex[order[1], c], order[1], order[0])
+    am = om.argmin_first(ex)
+    decided = ex[second, c] - ex[first, c] > E[first, c] + E[second, c]
+    assert np.all(i32[:512][decided] == am[decided])
+    b16 = (S64 ** 2).sum(1)[:, None] + (D64 ** 2).sum(1)[None, :] - 2 * (om.bf16_round(host(S)).astype(np.float64) @ D64.T)
+    top8 = np.argpartition(b16, 8, axis=0)[:8]
+    in8 = np.array([am[n] in top8[:, n] for n in c])
+    ok = decided & in8
+    assert np.all(ib[:512][ok] == am[ok])
+    # relative distance error of the rescored result against float64
+    rerr = np.abs(db[:512] - ex[ib[:512], c]) / ex[ib[:512], c]
+    print(f"C3: fp32/bf16 agreement {agree:.4f} over {n_img}; decided {decided.mean():.3f}; "
+          f"in proxy top-8 {in8.mean():.4f}; rescored rel. distance error max {rerr.max():.2e} "
+          f"median {np.median(rerr):.2e}")
+    assert agree >= 0.98 and decided.mean() >= 0.5 and in8.mean() >= 0.98
