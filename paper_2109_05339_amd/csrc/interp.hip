@@ -202,13 +202,31 @@ __global__ __launch_bounds__(kTile) void interp_tiled_kernel(
       if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
     }
     __syncthreads();
-    // rows of the brick: 8 rows at a time, 32 lanes along each row
-    const int lane32 = threadIdx.x & 31, rslot = threadIdx.x >> 5;
-    const int rows = e0 * e1;
-    for (int r = rslot; r < rows; r += kTile / 32) {
-      const int a = r / e1, b = r - a * e1;
-      const int64_t g = ((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf;
-      for (int c = lane32; c < e2; c += 32) brick[r * e2 + c] = u[g + wrap[2][c]];
+    // Cell c of the brick is (a, b, cc) = (c / (e1 e2), ..., c % e2); eight
+    // loads per thread are issued before their stores so their L2/MALL
+    // latencies overlap.  Quotients by the small extents use a float
+    // reciprocal: for c < 2^15 the exact quotient's distance from an integer
+    // is at least 1 / (2 e) >> the product's rounding error.
+    const int cells = e0 * e1 * e2;
+    const float inv_e2 = 1.0f / (float)e2, inv_e1 = 1.0f / (float)e1;
+    for (int c0 = threadIdx.x; c0 < cells; c0 += 8 * kTile) {
+      T v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c = c0 + k * kTile;
+        if (c < cells) {
+          const int r = (int)(((float)c + 0.5f) * inv_e2);
+          const int cc = c - r * e2;
+          const int a = (int)(((float)r + 0.5f) * inv_e1);
+          const int b = r - a * e1;
+          v[k] = u[((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + wrap[2][cc]];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c = c0 + k * kTile;
+        if (c < cells) brick[c] = v[k];
+      }
     }
   }
   float w0[W], w1[W], w2[W];
