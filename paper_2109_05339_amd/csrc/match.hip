@@ -67,7 +67,14 @@ __device__ inline float4 load_row4(const float *__restrict__ X, int64_t rows, in
 // kchunk).  Every split stores its partial tile; the last split of a tile
 // to arrive (per-tile counter) adds the partials in split order (a fixed
 // order, so results do not depend on arrival order) and runs the epilogue.
-__global__ __launch_bounds__(256, 2) void match_f32_kernel(
+//
+// 512 threads = 8 wavefronts as 2 (M) x 4 (N); each wavefront owns a 64 x 32
+// quarter-column of the 128 x 128 tile (two 32x32 MFMA accumulators plus two
+// per-K-step partials), which keeps the register count low enough for four
+// wavefronts per SIMD.
+constexpr int kF32Threads = 512;
+
+__global__ __launch_bounds__(kF32Threads, 2) void match_f32_kernel(
     const float *__restrict__ S, const float *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t m_offset,
     unsigned long long *__restrict__ keys, int tiles_m, int tiles_n, int vec, int splits,
@@ -76,39 +83,38 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
   __shared__ __attribute__((aligned(16))) float Bs[kBN * kLdF];
   __shared__ float sns[kBM], dns[kBN];
   __shared__ unsigned long long red[2][kBN];
+  __shared__ unsigned arrived;
 
   int tm, tn, split;
   tile_of_block(tiles_m, tiles_n, splits, tm, tn, split);
   const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int wm = wave >> 2, wn = wave & 3, lr = lane & 31, lh = lane >> 5;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(P, kbeg + kchunk);
 
-  float4 ra[4], rb[4];
+  float4 ra[2], rb[2];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 4;
+    for (int i = 0; i < 2; ++i) {
+      const int id = tid + kF32Threads * i, r = id >> 3, c = (id & 7) * 4;
       ra[i] = load_row4(S, M, row0 + r, kend, k0 + c, vec, P);
       rb[i] = load_row4(D, N, col0 + r, kend, k0 + c, vec, P);
     }
   };
 
-  floatx16 acc[2][2];
+  floatx16 acc[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
 
   gload(kbeg);
   for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 4;
+    for (int i = 0; i < 2; ++i) {
+      const int id = tid + kF32Threads * i, r = id >> 3, c = (id & 7) * 4;
       *reinterpret_cast<float4 *>(&As[r * kLdF + c]) = ra[i];
       *reinterpret_cast<float4 *>(&Bs[r * kLdF + c]) = rb[i];
     }
@@ -116,36 +122,28 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
     if (k0 + kBK < kend) gload(k0 + kBK);
     // Fresh partial sums per K step keep every accumulation chain short:
     // at most 2 kBK roundings inside the step plus one per step.
-    floatx16 part[2][2];
+    floatx16 part[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) part[i][j][r] = 0.f;
+      for (int r = 0; r < 16; ++r) part[i][r] = 0.f;
 #pragma unroll
     for (int kk = 0; kk < kBK / 8; ++kk) {
-      float4 a[2], b[2];
+      float4 a[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         a[i] = *reinterpret_cast<const float4 *>(&As[(wm * 64 + i * 32 + lr) * kLdF + kk * 8 + lh * 4]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const float4 *>(&Bs[(wn * 64 + j * 32 + lr) * kLdF + kk * 8 + lh * 4]);
+      const float4 b = *reinterpret_cast<const float4 *>(&Bs[(wn * 32 + lr) * kLdF + kk * 8 + lh * 4]);
       // Lane half lh supplies k = 4 lh + e for MFMA e: A and B use the same
       // permutation of the 8 k values, so the sum is unchanged.
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            part[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], b[j][e], part[i][j], 0, 0, 0);
+          part[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], b[e], part[i], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] += part[i][j];
+    for (int i = 0; i < 2; ++i) acc[i] += part[i];
   }
 
   if (splits > 1) {
@@ -155,50 +153,40 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) mine[((i * 2 + j) * 16 + r) * 256 + tid] = acc[i][j][r];
+      for (int r = 0; r < 16; ++r) mine[(i * 16 + r) * kF32Threads + tid] = acc[i][r];
     __threadfence();
-    __shared__ unsigned arrived;
     __syncthreads();
     if (tid == 0) arrived = atomicAdd(counters + tile, 1u);
     __syncthreads();
     if (arrived != (unsigned)(splits - 1)) return;
     __threadfence();
-    floatx16 sum[2][2];
+    floatx16 sum[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) sum[i][j][r] = 0.f;
+      for (int r = 0; r < 16; ++r) sum[i][r] = 0.f;
     for (int sp = 0; sp < splits; ++sp) {
       const float *part = partials + ((int64_t)tile * splits + sp) * (kBM * kBN);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            sum[i][j][r] += sp == split ? acc[i][j][r]
-                                        : __builtin_nontemporal_load(&part[((i * 2 + j) * 16 + r) * 256 + tid]);
+        for (int r = 0; r < 16; ++r)
+          sum[i][r] += sp == split ? acc[i][r]
+                                   : __builtin_nontemporal_load(&part[(i * 16 + r) * kF32Threads + tid]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = sum[i][j];
+    for (int i = 0; i < 2; ++i) acc[i] = sum[i];
     if (tid == 0) counters[tile] = 0u;  // ready for the next launch
   }
   if (tid < kBM) {
     sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
-  } else {
+  } else if (tid < kBM + kBN) {
     const int c = tid - kBM;
     dns[c] = col0 + c < N ? dn[col0 + c] : 0.f;
   }
   __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int cl = wn * 64 + j * 32 + lr;
+  {
+    const int cl = wn * 32 + lr;
     unsigned long long best = ~0ull;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -208,7 +196,7 @@ __global__ __launch_bounds__(256, 2) void match_f32_kernel(
         // 8 (r / 4) + 4 (lane / 32) + r % 4.
         const int rl = wm * 64 + i * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
         if (row0 + rl < M) {
-          const float d = fmaf(-2.0f, acc[i][j][r], sns[rl] + dns[cl]);
+          const float d = fmaf(-2.0f, acc[i][r], sns[rl] + dns[cl]);
           const unsigned long long key =
               ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)(row0 + rl));
           best = key < best ? key : best;
@@ -319,7 +307,7 @@ hipError_t launch_match_f32(const float *S, const float *D, const float *sn, con
     hipError_t e = launch_fill_zero(counters, (size_t)tiles * sizeof(unsigned), s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(match_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M, N,
+  hipLaunchKernelGGL(match_f32_kernel, dim3((unsigned)blocks), dim3(kF32Threads), 0, s, S, D, sn, dn, M, N,
                      P, (uint32_t)m_offset, keys, tiles_m, tiles_n, vec, splits, kchunk, partials,
                      counters);
   return hipGetLastError();

@@ -78,3 +78,19 @@ def test_real_domain_gradient():
     s.backward(gpu(gs))
     x = geometry.slice_points(f32(q), f32(det)).reshape(-1, 3)
     assert rel(host(mt.grad), nufft.nufft1(gs.astype(np.float64).ravel(), x, N, real=True)) <= 1e-5
+
+
+def test_slice_loss_with_registered_detector():
+    """The tiled kernels (registered detector) give the same loss and
+    gradient as the oracle."""
+    m, q, det, x, d, w = setup(N=13, n_img=5, n_det=24, seed=3)
+    plan = spfel.Plan(13, domain=spfel.COMPLEX, device=DEV)
+    plan.set_detector(gpu(det))
+    mt = gpu(m, torch.complex64).requires_grad_(True)
+    L = spfel.slice_loss(mt, gpu(q), None, gpu(d, torch.complex64), gpu(w), plan, chunk=2)
+    L.backward()
+    m64 = m.astype(np.complex128)
+    Lref = ograd.loss(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel())
+    assert abs(float(L.detach()) - Lref) <= 1e-4 * Lref
+    gref = ograd.grad(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel())
+    assert rel(host(mt.grad), gref) <= 1e-4
