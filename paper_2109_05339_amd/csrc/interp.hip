@@ -148,7 +148,7 @@ __device__ inline void block_minmax3(int (&mn)[3], int (&mx)[3], int (*sh)[6]) {
 }
 
 template <int W, bool CPLX>
-__global__ __launch_bounds__(kTile) void interp_tiled_kernel(
+__global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
     const void *__restrict__ u_, int nf, float beta, const float *__restrict__ quats, int64_t M,
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     void *__restrict__ out_, uint16_t *__restrict__ out_bf16) {
@@ -202,30 +202,69 @@ __global__ __launch_bounds__(kTile) void interp_tiled_kernel(
       if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
     }
     __syncthreads();
-    // Cell c of the brick is (a, b, cc) = (c / (e1 e2), ..., c % e2); eight
-    // loads per thread are issued before their stores so their L2/MALL
-    // latencies overlap.  Quotients by the small extents use a float
-    // reciprocal: for c < 2^15 the exact quotient's distance from an integer
-    // is at least 1 / (2 e) >> the product's rounding error.
-    const int cells = e0 * e1 * e2;
-    const float inv_e2 = 1.0f / (float)e2, inv_e1 = 1.0f / (float)e1;
-    for (int c0 = threadIdx.x; c0 < cells; c0 += 8 * kTile) {
-      T v[8];
+    // The brick is e0 x e1 rows of e2 cells.  When a row neither wraps nor
+    // reaches the end of a fine-grid row, it is moved in 16-byte segments
+    // (kVec cells; the last segment may read up to kVec - 1 cells past the
+    // brick row, still inside the same fine-grid row); otherwise one cell at
+    // a time.  Several loads per thread are in flight before their stores.
+    // Quotients by small extents use a float reciprocal: for n < 2^15 the
+    // exact quotient's distance from an integer is at least 1 / (2 e) >> the
+    // product's rounding error.
+    constexpr int kVec = 16 / (int)sizeof(T);
+    const int g2 = wrap[2][0];
+    const int nseg = (e2 + kVec - 1) / kVec;
+    const bool rows_contiguous = g2 + nseg * kVec <= nf;
+    const float inv_e1 = 1.0f / (float)e1;
+    if (rows_contiguous) {
+      const int items = e0 * e1 * nseg;
+      const float inv_ns = 1.0f / (float)nseg;
+      for (int c0 = threadIdx.x; c0 < items; c0 += 4 * kTile) {
+        T v[4][kVec];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int c = c0 + k * kTile;
-        if (c < cells) {
-          const int r = (int)(((float)c + 0.5f) * inv_e2);
-          const int cc = c - r * e2;
-          const int a = (int)(((float)r + 0.5f) * inv_e1);
-          const int b = r - a * e1;
-          v[k] = u[((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + wrap[2][cc]];
+        for (int k = 0; k < 4; ++k) {
+          const int c = c0 + k * kTile;
+          if (c < items) {
+            const int r = (int)(((float)c + 0.5f) * inv_ns);
+            const int q = c - r * nseg;
+            const int a = (int)(((float)r + 0.5f) * inv_e1);
+            const int b = r - a * e1;
+            const T *src = u + ((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + g2 + q * kVec;
+            __builtin_memcpy(&v[k][0], src, 16);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = c0 + k * kTile;
+          if (c < items) {
+            const int r = (int)(((float)c + 0.5f) * inv_ns);
+            const int q = c - r * nseg;
+#pragma unroll
+            for (int e = 0; e < kVec; ++e)
+              if (q * kVec + e < e2) brick[r * e2 + q * kVec + e] = v[k][e];
+          }
         }
       }
+    } else {
+      const int cells = e0 * e1 * e2;
+      const float inv_e2 = 1.0f / (float)e2;
+      for (int c0 = threadIdx.x; c0 < cells; c0 += 8 * kTile) {
+        T v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int c = c0 + k * kTile;
-        if (c < cells) brick[c] = v[k];
+        for (int k = 0; k < 8; ++k) {
+          const int c = c0 + k * kTile;
+          if (c < cells) {
+            const int r = (int)(((float)c + 0.5f) * inv_e2);
+            const int cc = c - r * e2;
+            const int a = (int)(((float)r + 0.5f) * inv_e1);
+            const int b = r - a * e1;
+            v[k] = u[((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + wrap[2][cc]];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int c = c0 + k * kTile;
+          if (c < cells) brick[c] = v[k];
+        }
       }
     }
   }
