@@ -88,8 +88,10 @@ def main() -> int:
     model = torch.from_numpy((alpha * m_host).astype(np.float32)).to(dev)
     dnorm = spfel.row_norm2(images)
     images_bf16 = images.to(torch.bfloat16)
-    ws = torch.empty((max(spfel.match_workspace_bytes(M, n_img, P, spfel.MATCH_FP32),
-                          spfel.match_workspace_bytes(M, n_img, P, spfel.MATCH_BF16_RESCORE8)),),
+    images_x3 = spfel.split_bf16(images)
+    ws = torch.empty((max(spfel.match_workspace_bytes(M, n_img, P, m)
+                          for m in (spfel.MATCH_FP32, spfel.MATCH_BF16_RESCORE8,
+                                    spfel.MATCH_BF16X3_RESCORE8)),),
                      dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     log(f"inputs ready in {time.time() - t0:.1f}s: M={M} n_img={n_img} P={P} N={N}")
@@ -120,6 +122,22 @@ def main() -> int:
         bi, bd = spfel.new_best(n_img, dev)
         if e: e[2].record(stream)
         spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
+                    slices_f32=S, images_f32=images, workspace=ws)
+        if e: e[3].record(stream)
+        if marks is not None:
+            marks.append(e)
+        return bi, bd
+
+    def step_bf16x3(marks=None):
+        e = [ev() for _ in range(4)] if marks is not None else None
+        if e: e[0].record(stream)
+        plan.set_model(model)
+        S, _, sn = plan.slice(ref_q, out=True, norms=True)
+        Sx = spfel.split_bf16(S)
+        if e: e[1].record(stream)
+        bi, bd = spfel.new_best(n_img, dev)
+        if e: e[2].record(stream)
+        spfel.match(Sx, sn, images_x3, dnorm, bi, bd, mode=spfel.MATCH_BF16X3_RESCORE8,
                     slices_f32=S, images_f32=images, workspace=ws)
         if e: e[3].record(stream)
         if marks is not None:
@@ -211,6 +229,18 @@ def main() -> int:
             "argmin_agreement_vs_fp32": agree,
         }
         log(f"bf16 step {max(wall_b, step_b):.3f} ms (match {match_b:.3f}), agreement {agree:.4f}")
+        log("timing split-bf16 (x3) + rescore path")
+        wall_x, step_x, slice_x, match_x = timed(step_bf16x3, max(5, args.steps // 2), 2)
+        bix, _ = step_bf16x3()
+        agree_x = float((bix == bi32).float().mean())
+        out["bf16x3_rescore"] = {
+            "ms_per_step": max(wall_x, step_x),
+            "match_ms": match_x,
+            "set_model+slice+split_ms": slice_x,
+            "pixel_comparisons_per_s": comps / (max(wall_x, step_x) * 1e-3),
+            "argmin_agreement_vs_fp32": agree_x,
+        }
+        log(f"bf16x3 step {max(wall_x, step_x):.3f} ms (match {match_x:.3f}), agreement {agree_x:.4f}")
         # type-1 spread of every image at its matched orientation (merge A* b)
         mq = ref_q[bi32.long()].contiguous()
         plan.merge_adjoint(mq, None, images)

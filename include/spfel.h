@@ -59,7 +59,7 @@ typedef enum {
 
 enum { SPFEL_REAL = 0, SPFEL_COMPLEX = 1 };
 enum { SPFEL_F32 = 0, SPFEL_BF16 = 1 };
-enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1 };
+enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1, SPFEL_MATCH_BF16X3_RESCORE8 = 2 };
 enum { SPFEL_MERGE_ACCUMULATE = 1, SPFEL_MERGE_DEFER = 2 };
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -142,6 +142,12 @@ size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P,
  *     smallest proxy distances, and those 8 are rescored exactly as above
  *     from slices_f32/images_f32 (required, float32).  The rescored
  *     distance is a chain of at most 10 + ceil(P/64) roundings.
+ *   mode SPFEL_MATCH_BF16X3_RESCORE8: as above, but slices and images are
+ *     2 x M x P and 2 x n_img x P bfloat16 (the hi and lo planes of
+ *     spfel_split_bf16) and the proxy products are hi.hi + lo.hi + hi.lo,
+ *     three BF16 matrix products per step; the proxy then carries about
+ *     16 significant bits, so the 8 candidates almost always contain the
+ *     float32 minimiser.
  * slice_norm2/image_norm2: float32 squared norms (spfel_row_norm2 of the
  * float32 data).  workspace: at least spfel_match_workspace_bytes bytes. */
 int spfel_match(const void *slices, const float *slice_norm2,
@@ -150,6 +156,11 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 const float *slices_f32, const float *images_f32,
                 int32_t *best_idx, float *best_dist, void *workspace,
                 size_t workspace_bytes, void *stream);
+
+/* Split float32 values into bfloat16 planes for SPFEL_MATCH_BF16X3_RESCORE8:
+ * out[0..n) = hi = bf16(x) and out[n..2n) = lo = bf16(x - hi), both round to
+ * nearest even.  out holds 2 n values. */
+int spfel_split_bf16(const float *x, int64_t n, uint16_t *out, void *stream);
 
 /* Section II-C, Eq. (2) right-hand side: the type-1 NUFFT (adjoint of
  * slicing) of values at the points R(quats[n]) det_q[p] (det_q NULL: the

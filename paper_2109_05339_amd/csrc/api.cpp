@@ -491,7 +491,8 @@ int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode) {
   if (M < 0 || n_img < 0 || P < 0) return 0;
   size_t b = match_f32_workspace_bytes(M, n_img, P);
-  if (mode == SPFEL_MATCH_BF16_RESCORE8) b = match_bf16_candidate_bytes(M, n_img);
+  if (mode == SPFEL_MATCH_BF16_RESCORE8 || mode == SPFEL_MATCH_BF16X3_RESCORE8)
+    b = match_bf16_candidate_bytes(M, n_img, mode == SPFEL_MATCH_BF16X3_RESCORE8);
   return b < 256 ? 256 : b;
 }
 
@@ -503,14 +504,16 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 size_t workspace_bytes, void *stream) {
   clear_error();
   if (M < 0 || n_img < 0 || P < 0 || m_offset < 0) return fail(SPFEL_EINVAL, "match: negative size");
-  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8)
+  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8 &&
+      mode != SPFEL_MATCH_BF16X3_RESCORE8)
     return fail(SPFEL_EINVAL, "match: unknown mode");
   if (m_offset + M > 0x7fffffffLL) return fail(SPFEL_ERANGE, "match: model index exceeds int32");
   if (P > (int64_t)1 << 30 || n_img > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "match: size too large");
   if (M == 0 || n_img == 0) return SPFEL_OK;
   if (!slices || !images || !slice_norm2 || !image_norm2 || !best_idx || !best_dist)
     return fail(SPFEL_EINVAL, "match: NULL pointer");
-  const bool bf = mode == SPFEL_MATCH_BF16_RESCORE8;
+  const bool bf = mode != SPFEL_MATCH_FP32;
+  const bool x3 = mode == SPFEL_MATCH_BF16X3_RESCORE8;
   if (bf && (!slices_f32 || !images_f32))
     return fail(SPFEL_EINVAL, "match: BF16 rescoring needs slices_f32 and images_f32");
   if (!aligned(slices, bf ? 2 : 4) || !aligned(images, bf ? 2 : 4) || !aligned(slice_norm2, 4) ||
@@ -533,12 +536,22 @@ int spfel_match(const void *slices, const float *slice_norm2,
   } else {
     auto *cand = static_cast<uint32_t *>(workspace);
     e = launch_match_bf16(static_cast<const uint16_t *>(slices), static_cast<const uint16_t *>(images),
-                          slice_norm2, image_norm2, M, n_img, P, cand, s);
+                          slice_norm2, image_norm2, M, n_img, P, cand, x3, s);
     if (e == hipSuccess)
       e = launch_rescore(cand, M, n_img, P, m_offset, slices_f32, images_f32, slice_norm2,
-                         image_norm2, best_idx, best_dist, s);
+                         image_norm2, best_idx, best_dist, x3, s);
   }
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "match: launch");
+}
+
+int spfel_split_bf16(const float *x, int64_t n, uint16_t *out, void *stream) {
+  clear_error();
+  if (n < 0) return fail(SPFEL_EINVAL, "split_bf16: negative size");
+  if (n == 0) return SPFEL_OK;
+  if (!x || !out) return fail(SPFEL_EINVAL, "split_bf16: NULL pointer");
+  if (!aligned(x, 4) || !aligned(out, 2)) return fail(SPFEL_EINVAL, "split_bf16: misaligned");
+  hipError_t e = launch_split_bf16(x, n, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "split_bf16: launch");
 }
 
 int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,

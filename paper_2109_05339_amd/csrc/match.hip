@@ -348,25 +348,35 @@ __device__ inline void insert8(unsigned long long (&top)[8], unsigned long long 
 
 // The large-tile kernel is used when its 256 x 256 tiles fill at least four
 // rounds of the chip's 256 resident blocks; otherwise 128 x 128 tiles.
-int match_bf16_tile_rows(int64_t M, int64_t N) {
+int match_bf16_tile_rows(int64_t M, int64_t N, bool x3) {
+  if (x3) return 128;
   const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
   return big >= 4 * 256 ? 256 : 128;
 }
 
-size_t match_bf16_candidate_bytes(int64_t M, int64_t N) {
-  const int64_t tr = match_bf16_tile_rows(M, N);
+size_t match_bf16_candidate_bytes(int64_t M, int64_t N, bool x3) {
+  const int64_t tr = match_bf16_tile_rows(M, N, x3);
   const int64_t tiles_m = (M + tr - 1) / tr;
   return (size_t)tiles_m * (size_t)N * 8 * sizeof(uint32_t);
 }
 
 // Candidate word: proxy-distance key with its 7 low bits replaced by the
 // row within the tile (a relative perturbation below 2^-16 of the proxy).
+// X3: S and D are [2][rows][P] planes (hi, lo) with hi + lo the float32
+// value to about 2^-16; the products hi.hi + lo.hi + hi.lo (lo.lo dropped)
+// run on the same BF16 matrix cores, three MFMAs per step.
+template <bool X3>
 __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
     const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
     int tiles_m, int tiles_n, int vec) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdH];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdH];
+  constexpr int kPlanes = X3 ? 2 : 1;
+  constexpr int kBKx = X3 ? 32 : kBKH;     // bf16 values of P per K step
+  constexpr int kLdx = kBKx + 8;           // LDS row stride
+  constexpr int kSeg = kBKx / 8;           // 16-byte segments per row and step
+  constexpr int kLoads = kBM * kSeg / 256; // segments per thread and operand
+  __shared__ __attribute__((aligned(16))) uint16_t As[kPlanes][kBM * kLdx];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kPlanes][kBN * kLdx];
   __shared__ float sns[kBM], dns[kBN];
   __shared__ uint32_t red[2][kBN][8];
 
@@ -376,14 +386,16 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
 
-  uint4 ra[4], rb[4];
+  uint4 ra[kPlanes][kLoads], rb[kPlanes][kLoads];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
-      ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
-      rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
-    }
+    for (int pl = 0; pl < kPlanes; ++pl)
+#pragma unroll
+      for (int i = 0; i < kLoads; ++i) {
+        const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
+        ra[pl][i] = load_row8h(S + pl * M * P, M, row0 + r, P, k0 + c, vec);
+        rb[pl][i] = load_row8h(D + pl * N * P, N, col0 + r, P, k0 + c, vec);
+      }
   };
 
   floatx16 acc[2][2];
@@ -395,30 +407,40 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   gload(0);
-  for (int64_t k0 = 0; k0 < P; k0 += kBKH) {
+  for (int64_t k0 = 0; k0 < P; k0 += kBKx) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
-      *reinterpret_cast<uint4 *>(&As[r * kLdH + c]) = ra[i];
-      *reinterpret_cast<uint4 *>(&Bs[r * kLdH + c]) = rb[i];
-    }
+    for (int pl = 0; pl < kPlanes; ++pl)
+#pragma unroll
+      for (int i = 0; i < kLoads; ++i) {
+        const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
+        *reinterpret_cast<uint4 *>(&As[pl][r * kLdx + c]) = ra[pl][i];
+        *reinterpret_cast<uint4 *>(&Bs[pl][r * kLdx + c]) = rb[pl][i];
+      }
     __syncthreads();
-    if (k0 + kBKH < P) gload(k0 + kBKH);
+    if (k0 + kBKx < P) gload(k0 + kBKx);
 #pragma unroll
-    for (int kk = 0; kk < kBKH / 16; ++kk) {
-      bf16x8 a[2], b[2];
+    for (int kk = 0; kk < kBKx / 16; ++kk) {
+      bf16x8 a[kPlanes][2], b[kPlanes][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 64 + i * 32 + lr) * kLdH + kk * 16 + lh * 8]);
+      for (int pl = 0; pl < kPlanes; ++pl) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 64 + j * 32 + lr) * kLdH + kk * 16 + lh * 8]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
+          a[pl][i] = *reinterpret_cast<const bf16x8 *>(&As[pl][(wm * 64 + i * 32 + lr) * kLdx + kk * 16 + lh * 8]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          b[pl][j] = *reinterpret_cast<const bf16x8 *>(&Bs[pl][(wn * 64 + j * 32 + lr) * kLdx + kk * 16 + lh * 8]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (X3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[kPlanes - 1][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
     }
   }
 
@@ -592,9 +614,17 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
 
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *sn,
                              const float *dn, int64_t M, int64_t N, int64_t P, uint32_t *cand,
-                             hipStream_t s) {
+                             bool x3, hipStream_t s) {
   const int vec = (P % 8 == 0) && al16(S) && al16(D);
-  if (match_bf16_tile_rows(M, N) == 256) {
+  if (x3) {
+    const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
+    const int64_t blocks = (int64_t)tiles_m * tiles_n;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(match_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn,
+                       dn, M, N, P, cand, tiles_m, tiles_n, vec);
+    return hipGetLastError();
+  }
+  if (match_bf16_tile_rows(M, N, false) == 256) {
     const int tiles_m = (int)((M + kBM2 - 1) / kBM2), tiles_n = (int)((N + kBN2 - 1) / kBN2);
     const int64_t blocks = (int64_t)tiles_m * tiles_n;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -605,7 +635,7 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
   const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
   const int64_t blocks = (int64_t)tiles_m * tiles_n;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(match_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
+  hipLaunchKernelGGL(match_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
                      N, P, cand, tiles_m, tiles_n, vec);
   return hipGetLastError();
 }
@@ -702,12 +732,32 @@ __global__ __launch_bounds__(256) void rescore_kernel(
 
 hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N, int64_t P, int64_t m_offset,
                           const float *S32, const float *D32, const float *sn, const float *dn,
-                          int32_t *best_idx, float *best_dist, hipStream_t s) {
-  const int tr = match_bf16_tile_rows(M, N);
+                          int32_t *best_idx, float *best_dist, bool x3, hipStream_t s) {
+  const int tr = match_bf16_tile_rows(M, N, x3);
   const int tiles_m = (int)((M + tr - 1) / tr);
   const int vec = (P % 4 == 0) && al16(S32) && al16(D32);
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, cand, tiles_m,
                      tr, N, P, (uint32_t)m_offset, S32, D32, sn, dn, best_idx, best_dist, vec);
+  return hipGetLastError();
+}
+
+// hi = bf16(x) (round to nearest even), lo = bf16(x - hi): hi + lo carries
+// x to about 16 significant bits.
+__global__ __launch_bounds__(256) void split_bf16_kernel(const float *__restrict__ x, int64_t n,
+                                                         uint16_t *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float v = x[i];
+    const uint16_t h = f32_to_bf16(v);
+    out[i] = h;
+    out[n + i] = f32_to_bf16(v - bf16_to_f32(h));
+  }
+}
+
+hipError_t launch_split_bf16(const float *x, int64_t n, uint16_t *out, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
 

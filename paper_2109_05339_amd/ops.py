@@ -17,7 +17,7 @@ from ._lib import check
 
 REAL, COMPLEX = 0, 1
 F32, BF16 = 0, 1
-MATCH_FP32, MATCH_BF16_RESCORE8 = 0, 1
+MATCH_FP32, MATCH_BF16_RESCORE8, MATCH_BF16X3_RESCORE8 = 0, 1, 2
 MERGE_ACCUMULATE, MERGE_DEFER = 1, 2
 
 
@@ -183,6 +183,15 @@ def row_norm2(x: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def split_bf16(x: torch.Tensor) -> torch.Tensor:
+    """(2, *x.shape) bfloat16 planes hi = bf16(x), lo = bf16(x - hi) of a
+    float32 tensor (for MATCH_BF16X3_RESCORE8)."""
+    _need(x, "x", torch.float32, x.device)
+    out = torch.empty((2,) + tuple(x.shape), dtype=torch.bfloat16, device=x.device)
+    check(_lib.lib().spfel_split_bf16(_p(x), x.numel(), _p(out), _stream(x.device)))
+    return out
+
+
 def match_workspace_bytes(M: int, n_img: int, P: int, mode: int = MATCH_FP32) -> int:
     return int(_lib.lib().spfel_match_workspace_bytes(M, n_img, P, mode))
 
@@ -200,19 +209,23 @@ def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
           workspace: Optional[torch.Tensor] = None) -> tuple:
     """Fold the nearest model image of each image into (best_idx, best_dist)
     in place and return them."""
-    dt = torch.bfloat16 if mode == MATCH_BF16_RESCORE8 else torch.float32
+    dt = torch.float32 if mode == MATCH_FP32 else torch.bfloat16
     dev = slices.device
     _need(slices, "slices", dt, dev)
     _need(images, "images", dt, dev)
-    if slices.dim() != 2 or images.dim() != 2 or slices.shape[1] != images.shape[1]:
-        raise ValueError("slices (M, P) and images (n_img, P) must share P")
-    M, P = slices.shape
-    n_img = images.shape[0]
+    planes = 2 if mode == MATCH_BF16X3_RESCORE8 else 1
+    if (slices.dim() != 1 + (planes > 1) or images.dim() != slices.dim()
+            or slices.shape[-1] != images.shape[-1]
+            or (planes > 1 and (slices.shape[0] != 2 or images.shape[0] != 2))):
+        raise ValueError("slices (M, P) and images (n_img, P) must share P "
+                         "(2 x M x P and 2 x n_img x P planes for BF16X3)")
+    M, P = slices.shape[-2], slices.shape[-1]
+    n_img = images.shape[-2]
     _need(slice_norm2, "slice_norm2", torch.float32, dev, (M,))
     _need(image_norm2, "image_norm2", torch.float32, dev, (n_img,))
     _need(best_idx, "best_idx", torch.int32, dev, (n_img,))
     _need(best_dist, "best_dist", torch.float32, dev, (n_img,))
-    if mode == MATCH_BF16_RESCORE8:
+    if mode != MATCH_FP32:
         _need(slices_f32, "slices_f32", torch.float32, dev, (M, P))
         _need(images_f32, "images_f32", torch.float32, dev, (n_img, P))
     need = match_workspace_bytes(M, n_img, P, mode)

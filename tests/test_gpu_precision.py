@@ -58,3 +58,53 @@ def test_c3_bf16_rescore_against_fp32_and_fp64():
           f"in proxy top-8 {in8.mean():.4f}; rescored rel. distance error max {rerr.max():.2e} "
           f"median {np.median(rerr):.2e}")
     assert agree >= 0.8 and decided.mean() >= 0.4 and in8.mean() >= 0.8
+
+
+def test_split_bf16_planes_are_exact_roundings():
+    g = np.random.default_rng(0)
+    x = np.concatenate([(g.standard_normal(100000) * 37).astype(np.float32),
+                        np.array([0.0, -0.0, 1.0, 65504.0, 1e-30, -3.3e-5], np.float32)])
+    out = host(spfel.split_bf16(gpu(x)).view(torch.int16)).view(np.uint16)
+    hi = om.bf16_round(x)
+    lo = om.bf16_round((x - hi).astype(np.float32))
+    np.testing.assert_array_equal(out[0], (hi.view(np.uint32) >> 16).astype(np.uint16))
+    np.testing.assert_array_equal(out[1], (lo.view(np.uint32) >> 16).astype(np.uint16))
+
+
+def test_c3_bf16x3_rescore_matches_fp32():
+    """The split-BF16 proxy (hi.hi + lo.hi + hi.lo) keeps the float32
+    minimiser among the 8 candidates: same argmin as the FP32 matcher on
+    every decided image of the 512-image subset and nearly all images."""
+    cfg = synth.config(3)
+    M, n_img, P = cfg.n_refs, cfg.n_images, cfg.n_pix
+    plan = spfel.Plan(cfg.n_model, device=DEV)
+    plan.set_detector(gpu(detector(cfg.n_det)))
+    plan.set_model(gpu(model(3)))
+    lam0 = plan.slice(gpu(synth.quaternions(cfg, "image_quats", n_img)))[0].clamp_(min=0)
+    alpha = synth.photon_scale(host(lam0), cfg.photons)
+    images = gpu(synth.poisson_counts(cfg, alpha * host(lam0)))
+    plan.set_model(gpu(alpha * model(3)))
+    S, _, sn = plan.slice(gpu(synth.quaternions(cfg, "ref_quats", M)), norms=True)
+    dn = spfel.row_norm2(images)
+    i32, _ = spfel.new_best(n_img, DEV)
+    d32 = torch.full((n_img,), float("inf"), device=DEV)
+    spfel.match(S, sn, images, dn, i32, d32)
+    ix, dx = spfel.new_best(n_img, DEV)
+    spfel.match(spfel.split_bf16(S), sn, spfel.split_bf16(images), dn, ix, dx,
+                mode=spfel.MATCH_BF16X3_RESCORE8, slices_f32=S, images_f32=images)
+    i32, ix = host(i32), host(ix)
+    S64 = host(S).astype(np.float64)
+    D64 = host(images[:512]).astype(np.float64)
+    ex = om.distances_expanded(S64, D64)
+    absdot = np.abs(S64) @ np.abs(D64).T
+    E = om.fp32_distance_bound((S64 ** 2).sum(1)[:, None], (D64 ** 2).sum(1)[None, :], absdot, 36 + P // 32)
+    c = np.arange(512)
+    o2 = np.argpartition(ex, 1, axis=0)[:2]
+    first = np.where(ex[o2[0], c] <= ex[o2[1], c], o2[0], o2[1])
+    second = np.where(ex[o2[0], c] <= ex[o2[1], c], o2[1], o2[0])
+    decided = ex[second, c] - ex[first, c] > E[first, c] + E[second, c]
+    am = om.argmin_first(ex)
+    assert np.all(ix[:512][decided] == am[decided])
+    agree = np.mean(ix == i32)
+    print(f"C3 bf16x3: agreement with fp32 {agree:.4f} over {n_img}")
+    assert agree >= 0.995
