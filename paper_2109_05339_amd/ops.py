@@ -202,6 +202,19 @@ def new_best(n_img: int, device) -> tuple:
             torch.full((n_img,), float("inf"), dtype=torch.float32, device=device))
 
 
+def match_sizes(slices_shape: tuple, images_shape: tuple, mode: int) -> tuple:
+    """(M, n_img, P) of matcher operands: (M, P) and (n_img, P), or for
+    MATCH_BF16X3_RESCORE8 the (2, M, P) and (2, n_img, P) hi/lo planes."""
+    ndim = 3 if mode == MATCH_BF16X3_RESCORE8 else 2
+    ok = (len(slices_shape) == ndim and len(images_shape) == ndim
+          and slices_shape[-1] == images_shape[-1]
+          and (ndim == 2 or (slices_shape[0] == 2 and images_shape[0] == 2)))
+    if not ok:
+        raise ValueError(f"matcher operands {slices_shape} and {images_shape} do not fit mode {mode}: "
+                         "(M, P) and (n_img, P), or (2, M, P) and (2, n_img, P) planes for BF16X3")
+    return slices_shape[-2], images_shape[-2], slices_shape[-1]
+
+
 def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
           image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
           m_offset: int = 0, mode: int = MATCH_FP32, slices_f32: Optional[torch.Tensor] = None,
@@ -213,14 +226,7 @@ def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
     dev = slices.device
     _need(slices, "slices", dt, dev)
     _need(images, "images", dt, dev)
-    planes = 2 if mode == MATCH_BF16X3_RESCORE8 else 1
-    if (slices.dim() != 1 + (planes > 1) or images.dim() != slices.dim()
-            or slices.shape[-1] != images.shape[-1]
-            or (planes > 1 and (slices.shape[0] != 2 or images.shape[0] != 2))):
-        raise ValueError("slices (M, P) and images (n_img, P) must share P "
-                         "(2 x M x P and 2 x n_img x P planes for BF16X3)")
-    M, P = slices.shape[-2], slices.shape[-1]
-    n_img = images.shape[-2]
+    M, n_img, P = match_sizes(tuple(slices.shape), tuple(images.shape), mode)
     _need(slice_norm2, "slice_norm2", torch.float32, dev, (M,))
     _need(image_norm2, "image_norm2", torch.float32, dev, (n_img,))
     _need(best_idx, "best_idx", torch.int32, dev, (n_img,))

@@ -116,3 +116,16 @@ def test_row_norm2_validation():
 def test_exceptions_map_codes():
     with pytest.raises(spfel.SpfelInvalidArgument):
         _lib.check(spfel.lib().spfel_row_norm2(None, 7, 1, 1, None, None))
+
+
+def test_match_operand_shapes():
+    from paper_2109_05339_amd.ops import match_sizes
+    assert match_sizes((1000, 4096), (256, 4096), spfel.MATCH_FP32) == (1000, 256, 4096)
+    assert match_sizes((1000, 4096), (256, 4096), spfel.MATCH_BF16_RESCORE8) == (1000, 256, 4096)
+    assert match_sizes((2, 1000, 4096), (2, 256, 4096), spfel.MATCH_BF16X3_RESCORE8) == (1000, 256, 4096)
+    for bad in [((1000, 4096), (256, 4095), spfel.MATCH_FP32),
+                ((2, 1000, 4096), (2, 256, 4096), spfel.MATCH_FP32),
+                ((1000, 4096), (256, 4096), spfel.MATCH_BF16X3_RESCORE8),
+                ((3, 1000, 4096), (2, 256, 4096), spfel.MATCH_BF16X3_RESCORE8)]:
+        with pytest.raises(ValueError):
+            match_sizes(*bad)
