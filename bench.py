@@ -32,6 +32,11 @@ if ROOT not in sys.path:
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# 256 CUs x 64 lanes x 2 flop x 2.4 GHz: FP32 fused multiply-add without the
+# packed (two-per-lane) form, which this build does not emit
+PEAK_FP32_VECTOR_TFLOPS = 78.6
+# algorithmic work of one interpolated point at w = 6: w^3 multiply-adds
+INTERP_FLOP_PER_POINT = 2 * 6 ** 3
 
 
 def log(msg: str) -> None:
@@ -47,6 +52,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip BF16 and spread side runs")
     ap.add_argument("--cpu-sample", type=int, default=200, help="orientations in the oracle sample")
+    ap.add_argument("--chunk", type=int, default=2048, help="orientations per pipeline chunk")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one step of each path and a plain 1 GiB "
                          "device copy (the copy calibrates FETCH_SIZE/WRITE_SIZE), no timing")
@@ -99,50 +105,25 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
-    def step_fp32(marks=None):
-        e = [ev() for _ in range(4)] if marks is not None else None
+    def step(mode, marks=None):
+        """One pass: set_model, then the slice->match pipeline over all
+        orientations (slicing of chunk k+1 overlaps matching of chunk k)."""
+        e = [ev() for _ in range(2)] if marks is not None else None
         if e: e[0].record(stream)
         plan.set_model(model)
-        S, _, sn = plan.slice(ref_q, out=True, norms=True)
-        if e: e[1].record(stream)
         bi, bd = spfel.new_best(n_img, dev)
-        if e: e[2].record(stream)
-        spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
-        if e: e[3].record(stream)
+        ims = {spfel.MATCH_FP32: images, spfel.MATCH_BF16_RESCORE8: images_bf16,
+               spfel.MATCH_BF16X3_RESCORE8: images_x3}[mode]
+        plan.orient(ref_q, ims, dnorm, bi, bd, mode=mode, chunk=args.chunk,
+                    images_f32=None if mode == spfel.MATCH_FP32 else images)
+        if e: e[1].record(stream)
         if marks is not None:
             marks.append(e)
         return bi, bd
 
-    def step_bf16(marks=None):
-        e = [ev() for _ in range(4)] if marks is not None else None
-        if e: e[0].record(stream)
-        plan.set_model(model)
-        S, Sb, sn = plan.slice(ref_q, out=True, bf16=True, norms=True)
-        if e: e[1].record(stream)
-        bi, bd = spfel.new_best(n_img, dev)
-        if e: e[2].record(stream)
-        spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
-                    slices_f32=S, images_f32=images, workspace=ws)
-        if e: e[3].record(stream)
-        if marks is not None:
-            marks.append(e)
-        return bi, bd
-
-    def step_bf16x3(marks=None):
-        e = [ev() for _ in range(4)] if marks is not None else None
-        if e: e[0].record(stream)
-        plan.set_model(model)
-        S, _, sn = plan.slice(ref_q, out=True, norms=True)
-        Sx = spfel.split_bf16(S)
-        if e: e[1].record(stream)
-        bi, bd = spfel.new_best(n_img, dev)
-        if e: e[2].record(stream)
-        spfel.match(Sx, sn, images_x3, dnorm, bi, bd, mode=spfel.MATCH_BF16X3_RESCORE8,
-                    slices_f32=S, images_f32=images, workspace=ws)
-        if e: e[3].record(stream)
-        if marks is not None:
-            marks.append(e)
-        return bi, bd
+    step_fp32 = lambda marks=None: step(spfel.MATCH_FP32, marks)  # noqa: E731
+    step_bf16 = lambda marks=None: step(spfel.MATCH_BF16_RESCORE8, marks)  # noqa: E731
+    step_bf16x3 = lambda marks=None: step(spfel.MATCH_BF16X3_RESCORE8, marks)  # noqa: E731
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -154,31 +135,63 @@ def main() -> int:
             fn(marks)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
-        slice_ms = float(np.mean([a.elapsed_time(b) for a, b, _, _ in marks]))
-        match_ms = float(np.mean([c.elapsed_time(d) for _, _, c, d in marks]))
-        step_ms = float(np.mean([a.elapsed_time(d) for a, _, _, d in marks]))
-        return wall * 1e3, step_ms, slice_ms, match_ms
+        step_ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
+        return wall * 1e3, step_ms
+
+    def kernel_times(reps):
+        """Unpipelined launches of the two hot kernels, each bracketed by
+        HIP events on its own (the current) stream."""
+        plan.set_model(model)
+        S, _, sn = plan.slice(ref_q, norms=True)
+        bi, bd = spfel.new_best(n_img, dev)
+        spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
+        torch.cuda.synchronize()
+        t_slice, t_match = [], []
+        for _ in range(reps):
+            a, b, c = ev(), ev(), ev()
+            a.record(stream)
+            plan.slice(ref_q, out=True, norms=False)
+            b.record(stream)
+            bi, bd = spfel.new_best(n_img, dev)
+            c.record(stream)
+            d = ev()
+            spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
+            d.record(stream)
+            t_slice.append((a, b))
+            t_match.append((c, d))
+        torch.cuda.synchronize()
+        return (float(np.mean([a.elapsed_time(b) for a, b in t_slice])),
+                float(np.mean([c.elapsed_time(d) for c, d in t_match])))
 
     if args.counters:
-        step_fp32()
+        kernel_times(1)
         step_bf16()
         plan.merge_adjoint(ref_q[:n_img].contiguous(), None, images)
         src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("counter run done: one fp32 step, one bf16 step, one merge, one 1 GiB copy")
+        log("counter run done: unpipelined slice + fp32 match, one bf16 step, one merge, one 1 GiB copy")
         print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 4}), flush=True)
         return 0
 
     log(f"timing fp32 path: {args.warmup} warmup + {args.steps} steps")
-    wall_ms, step_ms, slice_ms, match_ms = timed(step_fp32, args.steps, args.warmup)
+    wall_ms, step_ms = timed(step_fp32, args.steps, args.warmup)
     ms_per_step = max(wall_ms, step_ms)
     comps = float(M) * n_img * P
     value = comps / (ms_per_step * 1e-3)
+    slice_ms, match_ms = kernel_times(max(3, args.steps // 2))
     gemm_flops = 2.0 * comps
-    achieved = gemm_flops / (match_ms * 1e-3) / 1e12
-    log(f"fp32 step {ms_per_step:.3f} ms (slice+set_model {slice_ms:.3f}, match {match_ms:.3f})")
+    gemm_tf = gemm_flops / (match_ms * 1e-3) / 1e12
+    interp_tf = INTERP_FLOP_PER_POINT * M * P / (slice_ms * 1e-3) / 1e12
+    log(f"fp32 step {ms_per_step:.3f} ms; unpipelined slice {slice_ms:.3f} ms, match {match_ms:.3f} ms")
+    roof_match = {"kernel": "match_f32_kernel", "bound": "mfma", "achieved": gemm_tf,
+                  "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                  "frac": gemm_tf / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+    roof_interp = {"kernel": "interp_tiled_kernel", "bound": "alu", "achieved": interp_tf,
+                   "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                   "frac": interp_tf / PEAK_FP32_VECTOR_TFLOPS, "traffic": None}
+    dominant = roof_interp if slice_ms >= match_ms else roof_match
 
     out = {
         "metric": "slice+match pixel-comparisons/s",
@@ -197,50 +210,45 @@ def main() -> int:
             "workload": (f"{N}^3 float32 intensity model ({cfg.n_atoms} scatterers), "
                          f"{cfg.n_det}x{cfg.n_det} detector, {M} reference orientations, "
                          f"{n_img} Poisson images at {cfg.photons:g} photons/px; step = "
-                         "set_model + type-2 slicing + float32 distance GEMM with argmin"),
+                         "set_model + type-2 slicing + float32 distance GEMM with argmin, "
+                         f"pipelined over chunks of {args.chunk} orientations"),
             "M": M, "n_img": n_img, "P": P, "N": N, "kernel_width": 6, "upsampfac": 2.0,
+            "chunk": args.chunk,
         },
-        "breakdown_ms": {"set_model+slice": slice_ms, "match_fp32": match_ms},
+        "unpipelined_ms": {"slice_all": slice_ms, "match_fp32_all": match_ms},
         "nufft_type2_pts_per_s": M * P / (slice_ms * 1e-3),
-        "roofline": {
-            "kernel": "match_f32_kernel",
-            "bound": "mfma",
-            "achieved": achieved,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": None,
-        },
+        "roofline": dominant,
+        "roofline_kernels": [roof_interp, roof_match],
     }
 
     if not args.no_extras:
         bi32, _ = step_fp32()
-        log("timing bf16+rescore path")
-        wall_b, step_b, slice_b, match_b = timed(step_bf16, max(5, args.steps // 2), 2)
-        bib, _ = step_bf16()
-        agree = float((bib == bi32).float().mean())
-        out["bf16_rescore"] = {
-            "ms_per_step": max(wall_b, step_b),
-            "match_ms": match_b,
-            "set_model+slice_ms": slice_b,
-            "pixel_comparisons_per_s": comps / (max(wall_b, step_b) * 1e-3),
-            "gemm_tflops": gemm_flops / (match_b * 1e-3) / 1e12,
-            "gemm_frac_of_bf16_peak": gemm_flops / (match_b * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
-            "argmin_agreement_vs_fp32": agree,
-        }
-        log(f"bf16 step {max(wall_b, step_b):.3f} ms (match {match_b:.3f}), agreement {agree:.4f}")
-        log("timing split-bf16 (x3) + rescore path")
-        wall_x, step_x, slice_x, match_x = timed(step_bf16x3, max(5, args.steps // 2), 2)
-        bix, _ = step_bf16x3()
-        agree_x = float((bix == bi32).float().mean())
-        out["bf16x3_rescore"] = {
-            "ms_per_step": max(wall_x, step_x),
-            "match_ms": match_x,
-            "set_model+slice+split_ms": slice_x,
-            "pixel_comparisons_per_s": comps / (max(wall_x, step_x) * 1e-3),
-            "argmin_agreement_vs_fp32": agree_x,
-        }
-        log(f"bf16x3 step {max(wall_x, step_x):.3f} ms (match {match_x:.3f}), agreement {agree_x:.4f}")
+        for name, fn in (("bf16_rescore", step_bf16), ("bf16x3_rescore", step_bf16x3)):
+            log(f"timing {name} path")
+            wall_b, step_b = timed(fn, max(5, args.steps // 2), 2)
+            bib, _ = fn()
+            agree = float((bib == bi32).float().mean())
+            out[name] = {
+                "ms_per_step": max(wall_b, step_b),
+                "pixel_comparisons_per_s": comps / (max(wall_b, step_b) * 1e-3),
+                "argmin_agreement_vs_fp32": agree,
+            }
+            log(f"{name} step {max(wall_b, step_b):.3f} ms, agreement {agree:.4f}")
+        # BF16 GEMM kernel alone (unpipelined) on the same slices
+        plan.set_model(model)
+        S, Sb, sn = plan.slice(ref_q, bf16=True, norms=True)
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(5):
+            bi, bd = spfel.new_best(n_img, dev)
+            spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
+                        slices_f32=S, images_f32=images, workspace=ws)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) / 5
+        out["bf16_rescore"]["match_ms_unpipelined"] = t
+        del S, Sb, sn
         # type-1 spread of every image at its matched orientation (merge A* b)
         mq = ref_q[bi32.long()].contiguous()
         plan.merge_adjoint(mq, None, images)

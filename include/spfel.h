@@ -157,6 +157,32 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 int32_t *best_idx, float *best_dist, void *workspace,
                 size_t workspace_bytes, void *stream);
 
+/* Bytes of workspace spfel_orient needs for this chunk length. */
+size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
+                                    int mode);
+
+/* Sections II-A and II-B as one pipeline: slice the M model orientations in
+ * chunks of `chunk` and match every image against each chunk, folding into
+ * the running best (best_idx/best_dist, initialised by the caller as for
+ * spfel_match).  Each chunk's slices are computed on `aux_stream` into one of
+ * two workspace buffers while the previous chunk is matched on `stream`, so
+ * the VALU/LDS-bound interpolation and the matrix-core GEMM overlap; the
+ * model slices are never stored in full.  The result equals spfel_slice of
+ * each chunk followed by spfel_match with m_offset = chunk start.  REAL plans
+ * only; requires spfel_set_model.  images: n_img x P float32 (FP32 mode),
+ * bfloat16 (BF16 mode) or the 2 x n_img x P planes of spfel_split_bf16
+ * (BF16X3 mode; images_f32 then required, as for BF16).  Work queued on
+ * `stream` before the call is complete before any slice starts; every
+ * result is ordered before work later queued on `stream`.  `aux_stream` may
+ * equal `stream` (no overlap).  workspace: spfel_orient_workspace_bytes,
+ * 256-byte aligned; calls that overlap on the same plan race. */
+int spfel_orient(spfel_plan plan, const float *quats, int64_t M,
+                 const float *det_q, int64_t P, const void *images,
+                 const float *image_norm2, const float *images_f32,
+                 int64_t n_img, int mode, int64_t chunk, int32_t *best_idx,
+                 float *best_dist, void *workspace, size_t workspace_bytes,
+                 void *stream, void *aux_stream);
+
 /* Split float32 values into bfloat16 planes for SPFEL_MATCH_BF16X3_RESCORE8:
  * out[0..n) = hi = bf16(x) and out[n..2n) = lo = bf16(x - hi), both round to
  * nearest even.  out holds 2 n values. */

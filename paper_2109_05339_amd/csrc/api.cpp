@@ -168,7 +168,13 @@ static void free_plan(Plan *p) {
                   p->det_perm};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
+  hipEvent_t evs[] = {p->ev_start, p->ev_sliced[0], p->ev_sliced[1], p->ev_matched[0],
+                      p->ev_matched[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
 }
+
+static bool m_offset_overflow(int64_t M) { return M > 0x7fffffffLL; }
 
 static bool test_fail_alloc() {
   const char *e = std::getenv("SPFEL_TEST_FAIL_ALLOC");
@@ -252,6 +258,16 @@ int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
       return fail(SPFEL_ENOMEM, std::string("plan_create: hipMalloc: ") + hipGetErrorString(e));
     }
     p->bytes += r.bytes;
+  }
+  for (hipEvent_t *ev : {&p->ev_start, &p->ev_sliced[0], &p->ev_sliced[1], &p->ev_matched[0],
+                         &p->ev_matched[1]}) {
+    e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      *ev = nullptr;
+      free_plan(p);
+      delete p;
+      return hip_fail(e, "plan_create: hipEventCreate");
+    }
   }
   // Transform tables in float64, rounded once to float32.  The phase index
   // k l is reduced modulo nf exactly before the trigonometric evaluation.
@@ -552,6 +568,121 @@ int spfel_split_bf16(const float *x, int64_t n, uint16_t *out, void *stream) {
   if (!aligned(x, 4) || !aligned(out, 2)) return fail(SPFEL_EINVAL, "split_bf16: misaligned");
   hipError_t e = launch_split_bf16(x, n, out, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "split_bf16: launch");
+}
+
+
+// Slice buffers of one pipeline stage, carved from the caller's workspace.
+struct OrientStage {
+  float *f32 = nullptr;      // chunk x P
+  uint16_t *b16 = nullptr;   // chunk x P (BF16) or 2 x chunk x P (BF16X3)
+  float *norm = nullptr;     // chunk
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static size_t orient_stage_bytes(int64_t chunk, int64_t P, int mode) {
+  size_t b = align256((size_t)chunk * P * sizeof(float));
+  if (mode == SPFEL_MATCH_BF16_RESCORE8) b += align256((size_t)chunk * P * 2);
+  if (mode == SPFEL_MATCH_BF16X3_RESCORE8) b += align256((size_t)chunk * P * 4);
+  b += align256((size_t)chunk * sizeof(float));
+  return b;
+}
+
+// Largest matcher workspace over every chunk length up to `chunk` (the last
+// chunk may be shorter, and split-K choices depend on the tile count).
+static size_t match_ws_upto(int64_t chunk, int64_t n_img, int64_t P, int mode) {
+  size_t b = 0;
+  for (int64_t m = chunk; m > 0; m -= 128) b = std::max(b, spfel_match_workspace_bytes(m, n_img, P, mode));
+  return b;
+}
+
+size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P, int mode) {
+  if (chunk <= 0 || n_img < 0 || P < 0) return 0;
+  return 2 * orient_stage_bytes(chunk, P, mode) + align256(match_ws_upto(chunk, n_img, P, mode));
+}
+
+int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *det_q, int64_t P,
+                 const void *images, const float *image_norm2, const float *images_f32,
+                 int64_t n_img, int mode, int64_t chunk, int32_t *best_idx, float *best_dist,
+                 void *workspace, size_t workspace_bytes, void *stream, void *aux_stream) {
+  clear_error();
+  Plan *p = reinterpret_cast<Plan *>(plan);
+  if (!live(p)) return fail(SPFEL_ESTATE, "orient: not a live plan");
+  if (!p->model_set) return fail(SPFEL_ESTATE, "orient: set_model has not been called");
+  if (p->domain != SPFEL_REAL) return fail(SPFEL_EUNSUPPORTED, "orient: REAL plans only");
+  if (M < 0 || P < 0 || n_img < 0) return fail(SPFEL_EINVAL, "orient: negative size");
+  if (chunk <= 0) return fail(SPFEL_EINVAL, "orient: chunk must be positive");
+  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8 &&
+      mode != SPFEL_MATCH_BF16X3_RESCORE8)
+    return fail(SPFEL_EINVAL, "orient: unknown mode");
+  if (M == 0 || n_img == 0) return SPFEL_OK;
+  if (P == 0) return fail(SPFEL_EINVAL, "orient: P must be positive");
+  if (!det_q && P != p->det_P)
+    return fail(SPFEL_EINVAL, "orient: det_q is NULL and P differs from the registered detector");
+  if (!quats || !images || !image_norm2 || !best_idx || !best_dist)
+    return fail(SPFEL_EINVAL, "orient: NULL pointer");
+  if (mode != SPFEL_MATCH_FP32 && !images_f32)
+    return fail(SPFEL_EINVAL, "orient: BF16 modes need images_f32");
+  if (m_offset_overflow(M)) return fail(SPFEL_ERANGE, "orient: model index exceeds int32");
+  if (chunk > M) chunk = M;
+  const size_t need = spfel_orient_workspace_bytes(chunk, n_img, P, mode);
+  if (!workspace || workspace_bytes < need || !aligned(workspace, 256))
+    return fail(SPFEL_EINVAL, "orient: workspace smaller than spfel_orient_workspace_bytes or not 256-byte aligned");
+  DeviceGuard g(p->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "orient: hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStream_t a = static_cast<hipStream_t>(aux_stream);
+  if (a == s) a = s;  // one stream: the stages simply run in order
+  char *ws = static_cast<char *>(workspace);
+  OrientStage st[2];
+  const size_t sb = orient_stage_bytes(chunk, P, mode);
+  for (int k = 0; k < 2; ++k) {
+    char *b = ws + k * sb;
+    st[k].f32 = reinterpret_cast<float *>(b);
+    b += align256((size_t)chunk * P * sizeof(float));
+    if (mode != SPFEL_MATCH_FP32) {
+      st[k].b16 = reinterpret_cast<uint16_t *>(b);
+      b += align256((size_t)chunk * P * (mode == SPFEL_MATCH_BF16X3_RESCORE8 ? 4 : 2));
+    }
+    st[k].norm = reinterpret_cast<float *>(b);
+  }
+  void *mws = ws + 2 * sb;
+  const size_t mws_bytes = workspace_bytes - 2 * sb;
+  hipError_t e = hipEventRecord(p->ev_start, s);
+  if (e == hipSuccess && a != s) e = hipStreamWaitEvent(a, p->ev_start, 0);
+  if (e != hipSuccess) return hip_fail(e, "orient: event");
+  const int64_t nchunks = (M + chunk - 1) / chunk;
+  int rc = SPFEL_OK;
+  for (int64_t c = 0; c < nchunks && rc == SPFEL_OK; ++c) {
+    const int k = (int)(c & 1);
+    const int64_t m0 = c * chunk, mc = std::min(chunk, M - m0);
+    // slice stage on the auxiliary stream (after this buffer's last match)
+    if (c >= 2 && a != s) {
+      e = hipStreamWaitEvent(a, p->ev_matched[k], 0);
+      if (e != hipSuccess) return hip_fail(e, "orient: event");
+    }
+    uint16_t *b16 = mode == SPFEL_MATCH_BF16_RESCORE8 ? st[k].b16 : nullptr;
+    rc = spfel_slice(plan, quats + 4 * m0, mc, det_q, P, st[k].f32, b16, st[k].norm, a);
+    if (rc != SPFEL_OK) return rc;
+    if (mode == SPFEL_MATCH_BF16X3_RESCORE8) {
+      // planes of this chunk: hi at [0, mc P), lo at [mc P, 2 mc P)
+      rc = spfel_split_bf16(st[k].f32, mc * P, st[k].b16, a);
+      if (rc != SPFEL_OK) return rc;
+    }
+    e = hipEventRecord(p->ev_sliced[k], a);
+    if (e == hipSuccess && a != s) e = hipStreamWaitEvent(s, p->ev_sliced[k], 0);
+    if (e != hipSuccess) return hip_fail(e, "orient: event");
+    // match stage on the caller's stream
+    const void *sl = mode == SPFEL_MATCH_FP32 ? static_cast<const void *>(st[k].f32)
+                                              : static_cast<const void *>(st[k].b16);
+    rc = spfel_match(sl, st[k].norm, images, image_norm2, mc, n_img, P, m0, mode,
+                     mode == SPFEL_MATCH_FP32 ? nullptr : st[k].f32, images_f32, best_idx,
+                     best_dist, mws, mws_bytes, s);
+    if (rc != SPFEL_OK) return rc;
+    e = hipEventRecord(p->ev_matched[k], s);
+    if (e != hipSuccess) return hip_fail(e, "orient: event");
+  }
+  return rc;
 }
 
 int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,

@@ -45,6 +45,11 @@ struct Plan {
   bool model_set = false;
   bool pending = false;  // deferred spreads are waiting in acc
   size_t bytes = 0;
+  // Events of the two-stream orientation pipeline (spfel_orient): the main
+  // stream's start, each slice buffer's fill and release.
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_sliced[2] = {nullptr, nullptr};
+  hipEvent_t ev_matched[2] = {nullptr, nullptr};
 };
 
 // Points per detector tile of the tiled slicing/spreading kernels.

@@ -150,6 +150,49 @@ class Plan:
                                              _p(weights), _p(out), flags, _stream(self.device)))
         return out
 
+    def orient(self, quats: torch.Tensor, images: torch.Tensor, image_norm2: torch.Tensor,
+               best_idx: torch.Tensor, best_dist: torch.Tensor, mode: int = 0,
+               chunk: int = 2048, images_f32: Optional[torch.Tensor] = None,
+               det_q: Optional[torch.Tensor] = None, overlap: bool = True) -> tuple:
+        """Slice ``quats`` in chunks and match ``images`` against each chunk,
+        the slicing of one chunk overlapping the matching of the previous
+        on a second stream; folds into (best_idx, best_dist) in place."""
+        if self.domain != REAL:
+            raise ValueError("orient needs a REAL plan")
+        _need(quats, "quats", torch.float32, self.device)
+        det_q, P = self._detector(det_q)
+        dt = torch.float32 if mode == MATCH_FP32 else torch.bfloat16
+        _need(images, "images", dt, self.device)
+        n_img = images.shape[-2]
+        if images.shape[-1] != P:
+            raise ValueError("images and detector disagree on P")
+        _need(image_norm2, "image_norm2", torch.float32, self.device, (n_img,))
+        _need(best_idx, "best_idx", torch.int32, self.device, (n_img,))
+        _need(best_dist, "best_dist", torch.float32, self.device, (n_img,))
+        if mode != MATCH_FP32:
+            _need(images_f32, "images_f32", torch.float32, self.device, (n_img, P))
+        M = quats.shape[0]
+        c = max(1, min(chunk, M))
+        need = int(_lib.lib().spfel_orient_workspace_bytes(c, n_img, P, mode))
+        main = torch.cuda.current_stream(self.device)
+        aux = main
+        if overlap:
+            if getattr(self, "_aux", None) is None:
+                self._aux = torch.cuda.Stream(device=self.device)
+            aux = self._aux
+        ws = getattr(self, "_orient_ws", None)
+        if ws is None or ws.numel() < need:
+            if ws is not None:
+                ws.record_stream(aux)
+            ws = torch.empty((need,), dtype=torch.uint8, device=self.device)
+            self._orient_ws = ws
+        ws.record_stream(aux)
+        check(_lib.lib().spfel_orient(self._h, _p(quats), M, _p(det_q), P, _p(images),
+                                      _p(image_norm2), _p(images_f32), n_img, mode, c,
+                                      _p(best_idx), _p(best_dist), _p(ws), ws.numel(),
+                                      main.cuda_stream, aux.cuda_stream))
+        return best_idx, best_dist
+
     def weighted_residual(self, slices: torch.Tensor, images: torch.Tensor,
                           weights: Optional[torch.Tensor] = None, scale: float = 1.0,
                           residual: bool = True, loss: Optional[torch.Tensor] = None):
