@@ -52,7 +52,6 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip BF16 and spread side runs")
     ap.add_argument("--cpu-sample", type=int, default=200, help="orientations in the oracle sample")
-    ap.add_argument("--chunk", type=int, default=2048, help="orientations per pipeline chunk")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one step of each path and a plain 1 GiB "
                          "device copy (the copy calibrates FETCH_SIZE/WRITE_SIZE), no timing")
@@ -106,16 +105,21 @@ def main() -> int:
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
     def step(mode, marks=None):
-        """One pass: set_model, then the slice->match pipeline over all
-        orientations (slicing of chunk k+1 overlaps matching of chunk k)."""
+        """One pass: set_model, slice all orientations (with norms, and the
+        BF16 forms the mode needs), match every image against every slice."""
         e = [ev() for _ in range(2)] if marks is not None else None
         if e: e[0].record(stream)
         plan.set_model(model)
+        S, Sb, sn = plan.slice(ref_q, out=True, bf16=mode == spfel.MATCH_BF16_RESCORE8, norms=True)
         bi, bd = spfel.new_best(n_img, dev)
-        ims = {spfel.MATCH_FP32: images, spfel.MATCH_BF16_RESCORE8: images_bf16,
-               spfel.MATCH_BF16X3_RESCORE8: images_x3}[mode]
-        plan.orient(ref_q, ims, dnorm, bi, bd, mode=mode, chunk=args.chunk,
-                    images_f32=None if mode == spfel.MATCH_FP32 else images)
+        if mode == spfel.MATCH_FP32:
+            spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
+        elif mode == spfel.MATCH_BF16_RESCORE8:
+            spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=mode, slices_f32=S,
+                        images_f32=images, workspace=ws)
+        else:
+            spfel.match(spfel.split_bf16(S), sn, images_x3, dnorm, bi, bd, mode=mode,
+                        slices_f32=S, images_f32=images, workspace=ws)
         if e: e[1].record(stream)
         if marks is not None:
             marks.append(e)
@@ -210,10 +214,8 @@ def main() -> int:
             "workload": (f"{N}^3 float32 intensity model ({cfg.n_atoms} scatterers), "
                          f"{cfg.n_det}x{cfg.n_det} detector, {M} reference orientations, "
                          f"{n_img} Poisson images at {cfg.photons:g} photons/px; step = "
-                         "set_model + type-2 slicing + float32 distance GEMM with argmin, "
-                         f"pipelined over chunks of {args.chunk} orientations"),
+                         "set_model + type-2 slicing + float32 distance GEMM with argmin"),
             "M": M, "n_img": n_img, "P": P, "N": N, "kernel_width": 6, "upsampfac": 2.0,
-            "chunk": args.chunk,
         },
         "unpipelined_ms": {"slice_all": slice_ms, "match_fp32_all": match_ms},
         "nufft_type2_pts_per_s": M * P / (slice_ms * 1e-3),

@@ -74,13 +74,14 @@ __device__ inline float4 load_row4(const float *__restrict__ X, int64_t rows, in
 // wavefronts per SIMD.
 constexpr int kF32Threads = 512;
 
-__global__ __launch_bounds__(kF32Threads, 2) void match_f32_kernel(
+__global__ __launch_bounds__(kF32Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) void match_f32_kernel(
     const float *__restrict__ S, const float *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t m_offset,
     unsigned long long *__restrict__ keys, int tiles_m, int tiles_n, int vec, int splits,
     int64_t kchunk, float *__restrict__ partials, unsigned *__restrict__ counters) {
-  __shared__ __attribute__((aligned(16))) float As[kBM * kLdF];
-  __shared__ __attribute__((aligned(16))) float Bs[kBN * kLdF];
+  // double-buffered A/B stages: one barrier per K step
+  __shared__ __attribute__((aligned(16))) float As[2][kBM * kLdF];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kBN * kLdF];
   __shared__ float sns[kBM], dns[kBN];
   __shared__ unsigned long long red[2][kBN];
   __shared__ unsigned arrived;
@@ -109,17 +110,21 @@ __global__ __launch_bounds__(kF32Threads, 2) void match_f32_kernel(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
 
-  gload(kbeg);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
-    __syncthreads();
+  auto lstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int id = tid + kF32Threads * i, r = id >> 3, c = (id & 7) * 4;
-      *reinterpret_cast<float4 *>(&As[r * kLdF + c]) = ra[i];
-      *reinterpret_cast<float4 *>(&Bs[r * kLdF + c]) = rb[i];
+      *reinterpret_cast<float4 *>(&As[buf][r * kLdF + c]) = ra[i];
+      *reinterpret_cast<float4 *>(&Bs[buf][r * kLdF + c]) = rb[i];
     }
-    __syncthreads();
-    if (k0 + kBK < kend) gload(k0 + kBK);
+  };
+  gload(kbeg);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+    const bool more = k0 + kBK < kend;
+    if (more) gload(k0 + kBK);
     // Fresh partial sums per K step keep every accumulation chain short:
     // at most 2 kBK roundings inside the step plus one per step.
     floatx16 part[2];
@@ -127,13 +132,14 @@ __global__ __launch_bounds__(kF32Threads, 2) void match_f32_kernel(
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) part[i][r] = 0.f;
+    const float *A = As[buf], *B = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < kBK / 8; ++kk) {
       float4 a[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const float4 *>(&As[(wm * 64 + i * 32 + lr) * kLdF + kk * 8 + lh * 4]);
-      const float4 b = *reinterpret_cast<const float4 *>(&Bs[(wn * 32 + lr) * kLdF + kk * 8 + lh * 4]);
+        a[i] = *reinterpret_cast<const float4 *>(&A[(wm * 64 + i * 32 + lr) * kLdF + kk * 8 + lh * 4]);
+      const float4 b = *reinterpret_cast<const float4 *>(&B[(wn * 32 + lr) * kLdF + kk * 8 + lh * 4]);
       // Lane half lh supplies k = 4 lh + e for MFMA e: A and B use the same
       // permutation of the 8 k values, so the sum is unchanged.
 #pragma unroll
@@ -144,6 +150,9 @@ __global__ __launch_bounds__(kF32Threads, 2) void match_f32_kernel(
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) acc[i] += part[i];
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 
   if (splits > 1) {
