@@ -313,8 +313,6 @@ def bench_streaming(args, cfg, dev):
     model = torch.from_numpy((alpha * m_host).astype(np.float32)).to(dev)
     dnorm = spfel.row_norm2(images)
     images_bf16 = images.to(torch.bfloat16)
-    ws = torch.empty((spfel.match_workspace_bytes(C, n_img, P, spfel.MATCH_BF16_RESCORE8),),
-                     dtype=torch.uint8, device=dev)
     merged = torch.empty((N, N, N), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"workload 5 inputs ready in {time.time() - t0:.1f}s")
@@ -326,13 +324,8 @@ def bench_streaming(args, cfg, dev):
         if e: e[0].record(stream)
         plan.set_model(model)
         bi, bd = spfel.new_best(n_img, dev)
-        for c0 in range(0, M, C):
-            q = ref_q[c0:c0 + C]
-            S, Sb, sn = plan.slice(q, out=True, bf16=True, norms=True)
-            spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, m_offset=c0,
-                        mode=spfel.MATCH_BF16_RESCORE8, slices_f32=S, images_f32=images,
-                        workspace=ws)
-            del S, Sb, sn
+        plan.orient(ref_q, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8, chunk=C,
+                    images_f32=images, overlap=False)
         if e: e[1].record(stream)
         plan.merge_adjoint(ref_q[bi.long()].contiguous(), None, images, out=merged)
         if e: e[2].record(stream)
