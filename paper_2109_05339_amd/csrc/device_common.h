@@ -76,4 +76,13 @@ __device__ inline float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
+// Blocks are dealt round-robin to the 8 XCDs; this remaps the block id so
+// each XCD works through a contiguous range of the logical block order (and
+// neighbouring logical blocks share that XCD's L2).
+__device__ inline int64_t xcd_contiguous_block() {
+  const int64_t G = gridDim.x, bid = blockIdx.x;
+  const int64_t xcd = bid & 7, slot = bid >> 3, per = G >> 3, rem = G & 7;
+  return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+}
+
 }  // namespace spfel

@@ -158,8 +158,9 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];
 
-  const int64_t m = (int64_t)blockIdx.x / tiles;
-  const int tile = (int)((int64_t)blockIdx.x - m * tiles);
+  const int64_t vb = xcd_contiguous_block();
+  const int64_t m = vb / tiles;
+  const int tile = (int)(vb - m * tiles);
   const int64_t i = (int64_t)tile * kTile + threadIdx.x;
   const bool inb = i < P;
   double R[9];

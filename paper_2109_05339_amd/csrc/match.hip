@@ -258,12 +258,14 @@ static bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) =
 // Resident blocks of match_f32_kernel on the whole chip (256 CUs x 2).
 constexpr int kF32Slots = 512;
 
-// Number of K splits that best fills the chip's last round of blocks, with
-// each split at least 1024 values of P long.  Launches of four or more full
-// rounds lose little to their last round and are not split.
+// Number of K splits that best fills the chip's resident blocks, with each
+// split at least 1024 values of P long.  Only launches of under half a
+// round of tiles are split: blocks are dispatched dynamically, so a partial
+// last round costs less than the partial tiles' extra traffic (measured on
+// 1,264 tiles of K = 16,384: unsplit 5.8 ms, two splits 6.7 ms).
 int match_f32_splits(int64_t M, int64_t N, int64_t P) {
   const int64_t tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-  if (tiles >= 4 * kF32Slots) return 1;
+  if (2 * tiles >= kF32Slots) return 1;
   int best = 1;
   double best_eff = 0.0;
   for (int s = 1; s <= 4; ++s) {
@@ -500,13 +502,13 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
 }
 
 // Large-tile form for launches with many tiles: 256 x 256 tiles, each of
-// the 4 wavefronts owning a 128 x 128 quarter (16 MFMA accumulators, which
-// cuts LDS reads per MFMA in half against 64 x 64 quarters), A and B staged
-// in a double-buffered LDS ring with one barrier per K step.
+// 8 wavefronts (two per SIMD) owning a 128 x 64 block (8 MFMA accumulators:
+// 6 fragment reads per 8 MFMAs), A and B staged in a double-buffered LDS
+// ring with one barrier per K step.
 constexpr int kBM2 = 256, kBN2 = 256, kBK2 = 64, kLd2 = kBK2 + 8;
 constexpr int kStage2 = (kBM2 + kBN2) * kLd2;   // bf16 values per LDS stage
 
-__global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
+__global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
     const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
     int tiles_m, int tiles_n, int vec) {
@@ -515,14 +517,15 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
   int tm, tn, split;
   tile_of_block(tiles_m, tiles_n, 1, tm, tn, split);
   const int64_t row0 = (int64_t)tm * kBM2, col0 = (int64_t)tn * kBN2;
+  // 8 wavefronts as 2 (M) x 4 (N), each owning a 128 x 64 block of the tile
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int wm = wave >> 2, wn = wave & 3, lr = lane & 31, lh = lane >> 5;
 
-  uint4 ra[8], rb[8];
+  uint4 ra[4], rb[4];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 512 * i, r = id >> 3, c = (id & 7) * 8;
       ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
       rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
     }
@@ -531,18 +534,18 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
     uint16_t *As = smem + buf * kStage2;
     uint16_t *Bs = As + kBM2 * kLd2;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int id = tid + 256 * i, r = id >> 3, c = (id & 7) * 8;
+    for (int i = 0; i < 4; ++i) {
+      const int id = tid + 512 * i, r = id >> 3, c = (id & 7) * 8;
       *reinterpret_cast<uint4 *>(&As[r * kLd2 + c]) = ra[i];
       *reinterpret_cast<uint4 *>(&Bs[r * kLd2 + c]) = rb[i];
     }
   };
 
-  floatx16 acc[4][4];
+  floatx16 acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -557,17 +560,17 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
     const uint16_t *Bs = As + kBM2 * kLd2;
 #pragma unroll
     for (int kk = 0; kk < kBK2 / 16; ++kk) {
-      bf16x8 a[4], b[4];
+      bf16x8 a[4], b[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 128 + i * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 128 + j * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 64 + j * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (st + 1 < steps) lstore(buf ^ 1);
@@ -579,12 +582,12 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
   float *sns = reinterpret_cast<float *>(smem);
   float *dns = sns + kBM2;
   uint32_t *red = reinterpret_cast<uint32_t *>(dns + kBN2);   // [2][kBN2][8]
-  sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
-  dns[tid] = col0 + tid < N ? dn[col0 + tid] : 0.f;
+  if (tid < kBM2) sns[tid] = row0 + tid < M ? sn[row0 + tid] : 0.f;
+  else dns[tid - kBM2] = col0 + tid - kBM2 < N ? dn[col0 + tid - kBM2] : 0.f;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int cl = wn * 128 + j * 32 + lr;
+  for (int j = 0; j < 2; ++j) {
+    const int cl = wn * 64 + j * 32 + lr;
     uint32_t top[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) top[q] = ~0u;
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(256, 1) void match_bf16_big_kernel(
     }
   }
   __syncthreads();
-  if (col0 + tid < N) {
+  if (tid < kBN2 && col0 + tid < N) {
     uint32_t top[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) top[q] = red[tid * 8 + q];
@@ -637,7 +640,7 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
     const int tiles_m = (int)((M + kBM2 - 1) / kBM2), tiles_n = (int)((N + kBN2 - 1) / kBN2);
     const int64_t blocks = (int64_t)tiles_m * tiles_n;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(match_bf16_big_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn,
+    hipLaunchKernelGGL(match_bf16_big_kernel, dim3((unsigned)blocks), dim3(512), 0, s, S, D, sn,
                        dn, M, N, P, cand, tiles_m, tiles_n, vec);
     return hipGetLastError();
   }

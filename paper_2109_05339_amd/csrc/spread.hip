@@ -104,8 +104,9 @@ __global__ __launch_bounds__(kTile) void spread_tiled_kernel(
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];
 
-  const int64_t n = (int64_t)blockIdx.x / tiles;
-  const int tile = (int)((int64_t)blockIdx.x - n * tiles);
+  const int64_t vb = xcd_contiguous_block();
+  const int64_t n = vb / tiles;
+  const int tile = (int)(vb - n * tiles);
   const int64_t i = (int64_t)tile * kTile + threadIdx.x;
   const bool inb = i < P;
   double R[9];
@@ -285,8 +286,9 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
   __shared__ int wrap[3][64];
   __shared__ int cnt[66];                 // points per axis-1 cell, then exclusive offsets
 
-  const int64_t n = (int64_t)blockIdx.x / tiles;
-  const int tile = (int)((int64_t)blockIdx.x - n * tiles);
+  const int64_t vb = xcd_contiguous_block();
+  const int64_t n = vb / tiles;
+  const int tile = (int)(vb - n * tiles);
   const int64_t i = (int64_t)tile * kTile + threadIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool inb = i < P;

@@ -99,8 +99,9 @@ def test_workspace_sizes():
     ws = spfel.match_workspace_bytes
     assert ws(100, 256, 4096, spfel.MATCH_FP32) == 256 * 8
     assert ws(50000, 2048, 4096, spfel.MATCH_FP32) == 2048 * 8          # many rounds: no split-K
-    # 79 x 16 tiles fill 2.5 rounds of resident blocks: split K in two
-    assert ws(10000, 2048, 16384, spfel.MATCH_FP32) == 2048 * 8 + 5120 + 1264 * 2 * 128 * 128 * 4
+    assert ws(10000, 2048, 16384, spfel.MATCH_FP32) == 2048 * 8          # 2.5 rounds: no split-K
+    # 8 x 16 tiles are a quarter of a round of resident blocks: split K in four
+    assert ws(1000, 2048, 16384, spfel.MATCH_FP32) == 2048 * 8 + 512 + 128 * 4 * 128 * 128 * 4
     assert ws(1000, 256, 4096, spfel.MATCH_BF16_RESCORE8) == 8 * 256 * 8 * 4   # 8 m-tiles of 128
     assert ws(0, 0, 0, spfel.MATCH_FP32) == 256
 
