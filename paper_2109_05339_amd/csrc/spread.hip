@@ -79,185 +79,10 @@ __global__ __launch_bounds__(256) void spread_atomic_kernel(
 }
 
 
-// ---------------------------------------------------------------------------
-// Tiled spreading over the registered detector.  One block takes one image
-// and one compact detector tile: its points' contributions accumulate in an
-// LDS brick with LDS atomics, and the brick is then added to the fine grid
-// with one global atomic per nonzero cell (instead of w^3 per point).  A
-// brick beyond the LDS budget falls back to per-point global atomics.
-template <bool CPLX>
-constexpr int spread_brick_bytes() { return CPLX ? 65536 : 32768; }
-
 __device__ inline int wrap_mod_s(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
 }
-
-template <int W, bool CPLX>
-__global__ __launch_bounds__(kTile) void spread_tiled_kernel(
-    float *__restrict__ acc, int nf, float beta, const float *__restrict__ quats, int64_t n_img,
-    const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
-    const void *__restrict__ values_, const float *__restrict__ weights) {
-  constexpr int kComp = CPLX ? 2 : 1;
-  constexpr int kCap = spread_brick_bytes<CPLX>() / (4 * kComp);
-  __shared__ __attribute__((aligned(16))) float brick[kCap * kComp];
-  __shared__ int red[4][6];
-  __shared__ int wrap[3][64];
-
-  const int64_t vb = xcd_contiguous_block();
-  const int64_t n = vb / tiles;
-  const int tile = (int)(vb - n * tiles);
-  const int64_t i = (int64_t)tile * kTile + threadIdx.x;
-  const bool inb = i < P;
-  double R[9];
-  const bool qok = quat_rot(quats + 4 * n, R);
-  const double scale = (double)nf / (2.0 * M_PI);
-  int l0[3] = {0, 0, 0};
-  float frac[3] = {0.f, 0.f, 0.f};
-  bool valid = inb && qok;
-  float yr = 0.f, yi = 0.f;
-  if (valid) {
-    const double q0 = dets[3 * i], q1 = dets[3 * i + 1], q2 = dets[3 * i + 2];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double t = (R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2) * scale;
-      if (!(fabs(t) < 1e8)) {
-        valid = false;
-      } else {
-        const double c = ceil(t - 0.5 * W);
-        l0[d] = (int)c;
-        frac[d] = (float)(t - c);
-      }
-    }
-    const int64_t o = n * P + perm[i];
-    if (CPLX) {
-      const float2 v = static_cast<const float2 *>(values_)[o];
-      yr = v.x;
-      yi = v.y;
-    } else {
-      yr = static_cast<const float *>(values_)[o];
-    }
-    if (weights) {
-      const float wt = weights[o];
-      yr *= wt;
-      yi *= wt;
-    }
-  }
-  int mn[3], mx[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    mn[d] = valid ? l0[d] : 0x7fffffff;
-    mx[d] = valid ? l0[d] : -0x7fffffff;
-  }
-  // block-wide min/max of the support origins
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off));
-    }
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      red[threadIdx.x >> 6][d] = mn[d];
-      red[threadIdx.x >> 6][3 + d] = mx[d];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    mn[d] = min(min(red[0][d], red[1][d]), min(red[2][d], red[3][d]));
-    mx[d] = max(max(red[0][3 + d], red[1][3 + d]), max(red[2][3 + d], red[3][3 + d]));
-  }
-  if (!(mn[0] <= mx[0])) return;  // no valid point in the block (uniform)
-  const int e0 = mx[0] - mn[0] + W, e1 = mx[1] - mn[1] + W, e2 = mx[2] - mn[2] + W;
-  const bool use_lds = e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * e2 <= kCap;
-  float w0[W], w1[W], w2[W];
-  if (valid) {
-    es_weights<W>(frac[0], beta, w0);
-    es_weights<W>(frac[1], beta, w1);
-    es_weights<W>(frac[2], beta, w2);
-  }
-  if (use_lds) {
-    const int vol = e0 * e1 * e2 * kComp;
-    for (int c = threadIdx.x; c < vol; c += kTile) brick[c] = 0.f;
-    if (threadIdx.x < 64) {
-      const int t = threadIdx.x;
-      if (t < e0) wrap[0][t] = wrap_mod_s(mn[0] + t, nf);
-      if (t < e1) wrap[1][t] = wrap_mod_s(mn[1] + t, nf);
-      if (t < e2) wrap[2][t] = wrap_mod_s(mn[2] + t, nf);
-    }
-    __syncthreads();
-    if (valid) {
-      const int s0 = e1 * e2;
-      const int base = ((l0[0] - mn[0]) * e1 + (l0[1] - mn[1])) * e2 + (l0[2] - mn[2]);
-#pragma unroll
-      for (int a = 0; a < W; ++a) {
-        const float ra = w0[a] * yr, ia = w0[a] * yi;
-#pragma unroll
-        for (int b = 0; b < W; ++b) {
-          const float rb = w1[b] * ra, ib = w1[b] * ia;
-          const int row = base + a * s0 + b * e2;
-#pragma unroll
-          for (int c = 0; c < W; ++c) {
-            if (CPLX) {
-              atomicAdd(&brick[2 * (row + c)], w2[c] * rb);
-              atomicAdd(&brick[2 * (row + c) + 1], w2[c] * ib);
-            } else {
-              atomicAdd(&brick[row + c], w2[c] * rb);
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-    const int lane32 = threadIdx.x & 31, rslot = threadIdx.x >> 5;
-    const int rows = e0 * e1;
-    for (int r = rslot; r < rows; r += kTile / 32) {
-      const int a = r / e1, b = r - a * e1;
-      const int64_t g = ((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf;
-      for (int c = lane32; c < e2; c += 32) {
-        if (CPLX) {
-          const float vr = brick[2 * (r * e2 + c)], vi = brick[2 * (r * e2 + c) + 1];
-          if (vr != 0.f) unsafeAtomicAdd(acc + 2 * (g + wrap[2][c]), vr);
-          if (vi != 0.f) unsafeAtomicAdd(acc + 2 * (g + wrap[2][c]) + 1, vi);
-        } else {
-          const float v = brick[r * e2 + c];
-          if (v != 0.f) unsafeAtomicAdd(acc + g + wrap[2][c], v);
-        }
-      }
-    }
-    return;
-  }
-  if (!valid) return;
-  int g0[W], g1[W], g2[W];
-#pragma unroll
-  for (int a = 0; a < W; ++a) {
-    g0[a] = wrap_mod_s(l0[0] + a, nf);
-    g1[a] = wrap_mod_s(l0[1] + a, nf);
-    g2[a] = wrap_mod_s(l0[2] + a, nf);
-  }
-#pragma unroll
-  for (int a = 0; a < W; ++a) {
-    const float ra = w0[a] * yr, ia = w0[a] * yi;
-#pragma unroll
-    for (int b = 0; b < W; ++b) {
-      const float rb = w1[b] * ra, ib = w1[b] * ia;
-      const int64_t row = ((int64_t)g0[a] * nf + g1[b]) * nf;
-#pragma unroll
-      for (int c = 0; c < W; ++c) {
-        if (CPLX) {
-          unsafeAtomicAdd(acc + 2 * (row + g2[c]), w2[c] * rb);
-          unsafeAtomicAdd(acc + 2 * (row + g2[c]) + 1, w2[c] * ib);
-        } else {
-          unsafeAtomicAdd(acc + row + g2[c], w2[c] * rb);
-        }
-      }
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------------------
 // Matrix-core spreading over the registered detector.  For one image and one
