@@ -508,7 +508,7 @@ size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode
   if (M < 0 || n_img < 0 || P < 0) return 0;
   size_t b = match_f32_workspace_bytes(M, n_img, P);
   if (mode == SPFEL_MATCH_BF16_RESCORE8 || mode == SPFEL_MATCH_BF16X3_RESCORE8)
-    b = match_bf16_candidate_bytes(M, n_img, mode == SPFEL_MATCH_BF16X3_RESCORE8);
+    b = match_bf16_candidate_bytes(M, n_img);
   return b < 256 ? 256 : b;
 }
 
@@ -554,8 +554,9 @@ int spfel_match(const void *slices, const float *slice_norm2,
     e = launch_match_bf16(static_cast<const uint16_t *>(slices), static_cast<const uint16_t *>(images),
                           slice_norm2, image_norm2, M, n_img, P, cand, x3, s);
     if (e == hipSuccess)
-      e = launch_rescore(cand, M, n_img, P, m_offset, slices_f32, images_f32, slice_norm2,
-                         image_norm2, best_idx, best_dist, x3, s);
+      e = launch_rescore(cand, match_bf16_tile_rows(M, n_img, P, slices, images, x3), M, n_img,
+                         P, m_offset, slices_f32, images_f32, slice_norm2, image_norm2, best_idx,
+                         best_dist, s);
   }
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "match: launch");
 }

@@ -46,14 +46,22 @@ __device__ inline bool support_split(double t, int nf, int &base, float &frac) {
 }
 
 // ES kernel weights psi(frac - a), a = 0..W-1, with
-// psi(tau) = exp(beta (sqrt(1 - (2 tau / W)^2) - 1)).
+// psi(tau) = exp(beta (sqrt(1 - (2 tau / W)^2) - 1)) = 2^(c sqrt(r) - c),
+// c = beta log2(e).  The hardware square root and base-2 exponential
+// (about 1 ulp each) are used directly.  The exponent lies in [-c, 0]; its
+// rounding error, |c| 2^-24 ln 2, is below 1e-6 relative for the usual
+// beta = 2.30 w (w <= 8) and below 5e-6 at the largest accepted beta (80),
+// and psi >= 2^-c > 2^-126 stays a normal number, so no denormal handling
+// is needed.
 template <int W>
 __device__ inline void es_weights(float frac, float beta, float (&wt)[W]) {
+  const float c = beta * 1.44269504088896341f;
+  const float k = 2.0f / (float)W;
 #pragma unroll
   for (int a = 0; a < W; ++a) {
-    const float z = (frac - (float)a) * (2.0f / (float)W);
-    const float r = fmaxf(1.0f - z * z, 0.0f);
-    wt[a] = __expf(beta * (sqrtf(r) - 1.0f));
+    const float z = fmaf(frac, k, -(float)a * k);
+    const float r = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+    wt[a] = __builtin_amdgcn_exp2f(fmaf(c, __builtin_amdgcn_sqrtf(r), -c));
   }
 }
 
@@ -74,6 +82,45 @@ __device__ inline uint32_t float_key(float f) {
 }
 __device__ inline float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// Minimum over the 64 lanes of a wavefront (all lanes active), returned to
+// every lane.  DPP row operations do the work on the vector ALU: two
+// quad-permute butterflies and the half/full row mirrors give each row of 16
+// lanes its minimum; broadcasts of lane 15 into rows 1 and 3, then of lane 31
+// into rows 2 and 3, leave the wavefront's minimum in lane 63.
+__device__ inline int wave_min(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Block-wide minimum and maximum of three ints over a block of four
+// wavefronts; sh is 4 x 6 ints of shared memory.  Ends with a barrier.
+__device__ inline void block_minmax3(int (&mn)[3], int (&mx)[3], int (*sh)[6]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = wave_min(mn[d]);
+    mx[d] = -wave_min(-mx[d]);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sh[wave][d] = mn[d];
+      sh[wave][3 + d] = mx[d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = min(min(sh[0][d], sh[1][d]), min(sh[2][d], sh[3][d]));
+    mx[d] = max(max(sh[0][3 + d], sh[1][3 + d]), max(sh[2][3 + d], sh[3][3 + d]));
+  }
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; this remaps the block id so

@@ -99,17 +99,20 @@ size_t match_f32_workspace_bytes(int64_t M, int64_t N, int64_t P);
 hipError_t launch_match_f32(const float *S, const float *D, const float *sn,
                             const float *dn, int64_t M, int64_t N, int64_t P,
                             int64_t m_offset, void *workspace, hipStream_t s);
-// x3: S and D are [2][rows][P] (hi, lo) planes.
-size_t match_bf16_candidate_bytes(int64_t M, int64_t N, bool x3);
+// x3: S and D are [2][rows][P] (hi, lo) planes.  The candidate buffer
+// holds 8 words per image per tile of tile_rows model images (128 or 256,
+// match_bf16_tile_rows); its size is that of the 128-row tiling.
+int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D,
+                         bool x3);
+size_t match_bf16_candidate_bytes(int64_t M, int64_t N);
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D,
                              const float *sn, const float *dn, int64_t M,
                              int64_t N, int64_t P, uint32_t *cand, bool x3,
                              hipStream_t s);
-hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N,
+hipError_t launch_rescore(const uint32_t *cand, int tile_rows, int64_t M, int64_t N,
                           int64_t P, int64_t m_offset, const float *S32,
                           const float *D32, const float *sn, const float *dn,
-                          int32_t *best_idx, float *best_dist, bool x3,
-                          hipStream_t s);
+                          int32_t *best_idx, float *best_dist, hipStream_t s);
 hipError_t launch_split_bf16(const float *x, int64_t n, uint16_t *out,
                              hipStream_t s);
 

@@ -117,34 +117,16 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
 template <bool CPLX>
 constexpr int brick_bytes() { return CPLX ? 65536 : 32768; }
 
+// LDS banks (4 bytes wide) and the number of candidate brick layouts.
+#ifndef SPFEL_LDS_BANKS
+#define SPFEL_LDS_BANKS 64
+#endif
+constexpr int kBanks = SPFEL_LDS_BANKS;
+constexpr int kLayouts = 16;
+
 __device__ inline int wrap_mod(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
-}
-
-// Block-wide min and max of three ints (kTile threads, 4 wavefronts).
-__device__ inline void block_minmax3(int (&mn)[3], int (&mx)[3], int (*sh)[6]) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off));
-    }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      sh[wave][d] = mn[d];
-      sh[wave][3 + d] = mx[d];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    mn[d] = min(min(sh[0][d], sh[1][d]), min(sh[2][d], sh[3][d]));
-    mx[d] = max(max(sh[0][3 + d], sh[1][3 + d]), max(sh[2][3 + d], sh[3][3 + d]));
-  }
 }
 
 template <int W, bool CPLX>
@@ -157,10 +139,11 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   __shared__ __attribute__((aligned(16))) T brick[kCap];
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];
+  __shared__ int layout[1];
 
-  const int64_t vb = xcd_contiguous_block();
+  const int vb = (int)xcd_contiguous_block();   // the grid has < 2^31 blocks
   const int64_t m = vb / tiles;
-  const int tile = (int)(vb - m * tiles);
+  const int tile = vb - (int)m * tiles;
   const int64_t i = (int64_t)tile * kTile + threadIdx.x;
   const bool inb = i < P;
   double R[9];
@@ -192,35 +175,95 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   block_minmax3(mn, mx, red);
   const bool any = mn[0] <= mx[0];
   const int e0 = mx[0] - mn[0] + W, e1 = mx[1] - mn[1] + W, e2 = mx[2] - mn[2] + W;
-  const bool use_lds = any && e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * e2 <= kCap;
+  // Brick layout: cell (x0, x1, x2) at x0 * s0 + x1 * p2 + x2, with the row
+  // pitch p2 >= p4 (e2 rounded up to whole 16-byte segments, so a segment
+  // store never spills into the next row) and the plane stride
+  // s0 >= e1 * p2.  For real cells the small paddings are chosen per block:
+  // a wavefront's 64 lanes read 64 cells at a common offset from their
+  // support origins, so the LDS bank conflicts of every gather read are
+  // those of the lanes' origin addresses.  The first wavefront scores each
+  // candidate layout by letting every lane write its origin address into a
+  // table slot named by the address's bank and read the slot back: a lane
+  // that finds another address there shares its bank with a different
+  // cell.  The candidate with the fewest such lanes wins (ties: the first);
+  // the other wavefronts' patches lie next to the first's, under the same
+  // rotation, and share its choice.
+  constexpr int kVec = 16 / (int)sizeof(T);
+  const int nseg = (e2 + kVec - 1) / kVec;
+  const int p4 = nseg * kVec;
+  const bool use_lds = any && e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * p4 <= kCap;
+  const bool choose = !CPLX && use_lds && e0 * (e1 * (p4 + 3) + 3) <= kCap;
+  if (use_lds && threadIdx.x < 64) {
+    // fine-grid offsets of every brick plane, row and column, wrapped once
+    // per block (n_f <= 1022, so n_f^3 cells index in 32 bits)
+    const int t = threadIdx.x;
+    if (t < e0) wrap[0][t] = wrap_mod(mn[0] + t, nf) * nf * nf;
+    if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t, nf) * nf;
+    if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
+    if (choose) {
+      // candidate c = 4 pe + d: p2 = p4 + pe, s0 = e1 p2 + d, so the origin
+      // address is row * (p4 + pe) + d * x0 + x2 with row = x0 e1 + x1
+      const int x0 = l0[0] - mn[0], row = x0 * e1 + (l0[1] - mn[1]);
+      int *tab = reinterpret_cast<int *>(brick);   // kLayouts x (kBanks + 1) slots
+      int addr[kLayouts], slot[kLayouts];
+      int a_pe = row * p4 + (l0[2] - mn[2]);
+#pragma unroll
+      for (int pe = 0; pe < 4; ++pe) {
+        int a = a_pe;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int c = 4 * pe + d;
+          addr[c] = a;
+          slot[c] = c * (kBanks + 1) + (valid ? (a & (kBanks - 1)) : kBanks);
+          tab[slot[c]] = a;
+          a += x0;
+        }
+        a_pe += row;
+      }
+      // The read-back must see the other lanes' writes, not this lane's own
+      // store forwarded by the compiler: a compiler memory barrier keeps the
+      // loads after the stores, and a wavefront's LDS accesses complete in
+      // order, so every write has landed before the reads.
+      __asm__ __volatile__("" ::: "memory");
+      int got[kLayouts];
+#pragma unroll
+      for (int c = 0; c < kLayouts; ++c) got[c] = tab[slot[c]];
+      int best_key = 0x7fffffff;
+#pragma unroll
+      for (int c = 0; c < kLayouts; ++c) {
+        const int n = __popcll(__ballot(valid && got[c] != addr[c]));
+        best_key = min(best_key, (n << 4) | c);
+      }
+      if (t == 0) layout[0] = best_key & 15;
+    }
+  }
+  if (use_lds) __syncthreads();
+  int p2 = p4, s0 = e1 * p4;
+  if (choose) {
+    const int best = layout[0];
+    p2 = p4 + (best >> 2);
+    s0 = e1 * p2 + (best & 3);
+  }
   const T *u = static_cast<const T *>(u_);
   if (use_lds) {
-    // fine-grid index of every brick row/column, wrapped once per block
-    if (threadIdx.x < 64) {
-      const int t = threadIdx.x;
-      if (t < e0) wrap[0][t] = wrap_mod(mn[0] + t, nf);
-      if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t, nf);
-      if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
-    }
-    __syncthreads();
-    // The brick is e0 x e1 rows of e2 cells.  When a row neither wraps nor
-    // reaches the end of a fine-grid row, it is moved in 16-byte segments
-    // (kVec cells; the last segment may read up to kVec - 1 cells past the
-    // brick row, still inside the same fine-grid row); otherwise one cell at
-    // a time.  Several loads per thread are in flight before their stores.
-    // Quotients by small extents use a float reciprocal: for n < 2^15 the
-    // exact quotient's distance from an integer is at least 1 / (2 e) >> the
-    // product's rounding error.
-    constexpr int kVec = 16 / (int)sizeof(T);
+    // The brick holds e0 x e1 rows of e2 cells.  When a row neither wraps
+    // nor reaches the end of a fine-grid row, it is moved in 16-byte
+    // segments (kVec cells; the last segment may read up to kVec - 1 cells
+    // past the brick row, still inside the same fine-grid row, into the
+    // row's padding); otherwise one cell at a time.  Several loads per
+    // thread are in flight before their stores.  Quotients by small extents
+    // e <= 64 use a float reciprocal: the exact quotient (n + 1/2) / e lies
+    // at least 1 / (2 e) >= 1/128 from an integer, far above the product's
+    // error (quotients below 2^13, the reciprocal within 1 ulp).
     const int g2 = wrap[2][0];
-    const int nseg = (e2 + kVec - 1) / kVec;
-    const bool rows_contiguous = g2 + nseg * kVec <= nf;
-    const float inv_e1 = 1.0f / (float)e1;
+    const bool rows_contiguous = g2 + p4 <= nf;
+    const float inv_e1 = __builtin_amdgcn_rcpf((float)e1);
     if (rows_contiguous) {
       const int items = e0 * e1 * nseg;
-      const float inv_ns = 1.0f / (float)nseg;
+      const float inv_ns = __builtin_amdgcn_rcpf((float)nseg);
       for (int c0 = threadIdx.x; c0 < items; c0 += 4 * kTile) {
         T v[4][kVec];
+        int dst[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int c = c0 + k * kTile;
@@ -229,25 +272,22 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
             const int q = c - r * nseg;
             const int a = (int)(((float)r + 0.5f) * inv_e1);
             const int b = r - a * e1;
-            const T *src = u + ((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + g2 + q * kVec;
+            const T *src = u + (wrap[0][a] + wrap[1][b] + g2 + q * kVec);
             __builtin_memcpy(&v[k][0], src, 16);
+            dst[k] = a * s0 + b * p2 + q * kVec;
           }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int c = c0 + k * kTile;
-          if (c < items) {
-            const int r = (int)(((float)c + 0.5f) * inv_ns);
-            const int q = c - r * nseg;
+          if (c0 + k * kTile < items) {
 #pragma unroll
-            for (int e = 0; e < kVec; ++e)
-              if (q * kVec + e < e2) brick[r * e2 + q * kVec + e] = v[k][e];
+            for (int e = 0; e < kVec; ++e) brick[dst[k] + e] = v[k][e];
           }
         }
       }
     } else {
       const int cells = e0 * e1 * e2;
-      const float inv_e2 = 1.0f / (float)e2;
+      const float inv_e2 = __builtin_amdgcn_rcpf((float)e2);
       for (int c0 = threadIdx.x; c0 < cells; c0 += 8 * kTile) {
         T v[8];
 #pragma unroll
@@ -258,13 +298,17 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
             const int cc = c - r * e2;
             const int a = (int)(((float)r + 0.5f) * inv_e1);
             const int b = r - a * e1;
-            v[k] = u[((int64_t)wrap[0][a] * nf + wrap[1][b]) * nf + wrap[2][cc]];
+            v[k] = u[wrap[0][a] + wrap[1][b] + wrap[2][cc]];
           }
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int c = c0 + k * kTile;
-          if (c < cells) brick[c] = v[k];
+          if (c < cells) {
+            const int r = (int)(((float)c + 0.5f) * inv_e2);
+            const int a = (int)(((float)r + 0.5f) * inv_e1);
+            brick[a * s0 + (r - a * e1) * p2 + (c - r * e2)] = v[k];
+          }
         }
       }
     }
@@ -290,14 +334,13 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   }
   float sr = 0.f, si = 0.f;
   if (use_lds) {
-    const int s0 = e1 * e2;
-    const int base = ((l0[0] - mn[0]) * e1 + (l0[1] - mn[1])) * e2 + (l0[2] - mn[2]);
+    const int base = (l0[0] - mn[0]) * s0 + (l0[1] - mn[1]) * p2 + (l0[2] - mn[2]);
 #pragma unroll
     for (int a = 0; a < W; ++a) {
       float pr = 0.f, pi = 0.f;
 #pragma unroll
       for (int b = 0; b < W; ++b) {
-        const T *row = brick + base + a * s0 + b * e2;
+        const T *row = brick + base + a * s0 + b * p2;
         float rr = 0.f, ri = 0.f;
 #pragma unroll
         for (int c = 0; c < W; ++c) {

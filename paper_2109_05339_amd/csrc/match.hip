@@ -358,16 +358,19 @@ __device__ inline void insert8(unsigned long long (&top)[8], unsigned long long 
 }
 
 // The large-tile kernel is used when its 256 x 256 tiles fill at least four
-// rounds of the chip's 256 resident blocks; otherwise 128 x 128 tiles.
-int match_bf16_tile_rows(int64_t M, int64_t N, bool x3) {
-  if (x3) return 128;
+// rounds of the chip's 256 resident blocks, P is a whole number of its
+// 64-wide K steps and both operands are 16-byte aligned; otherwise
+// 128 x 128 tiles.
+int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D,
+                         bool x3) {
+  if (x3 || P % 64 != 0 || !al16(S) || !al16(D)) return 128;
   const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
   return big >= 4 * 256 ? 256 : 128;
 }
 
-size_t match_bf16_candidate_bytes(int64_t M, int64_t N, bool x3) {
-  const int64_t tr = match_bf16_tile_rows(M, N, x3);
-  const int64_t tiles_m = (M + tr - 1) / tr;
+// Candidate buffer for the 128-row tiling, the larger of the two.
+size_t match_bf16_candidate_bytes(int64_t M, int64_t N) {
+  const int64_t tiles_m = (M + 127) / 128;
   return (size_t)tiles_m * (size_t)N * 8 * sizeof(uint32_t);
 }
 
@@ -503,15 +506,25 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
 
 // Large-tile form for launches with many tiles: 256 x 256 tiles, each of
 // 8 wavefronts (two per SIMD) owning a 128 x 64 block (8 MFMA accumulators:
-// 6 fragment reads per 8 MFMAs), A and B staged in a double-buffered LDS
-// ring with one barrier per K step.
-constexpr int kBM2 = 256, kBN2 = 256, kBK2 = 64, kLd2 = kBK2 + 8;
-constexpr int kStage2 = (kBM2 + kBN2) * kLd2;   // bf16 values per LDS stage
+// 6 fragment reads per 8 MFMAs).  A and B stream from global memory straight
+// into a double-buffered LDS ring (global_load_lds_dwordx4: each lane's 16
+// bytes land at the instruction's LDS base + 16 x lane), one barrier per K
+// step.  Rows are 128 bytes (64 bf16) without padding; the 16-byte chunk c
+// of row r is stored at chunk c ^ f(r), f(r) = (r & 7) ^ ((r >> 3) & 1), so
+// the 16 consecutive rows one fragment read touches fall in distinct bank
+// groups.  Fragments are double-buffered in registers: the reads for the
+// next 16-wide K slice are issued before the current slice's MFMAs.
+// Requires P % 64 == 0 and 16-byte aligned rows; rows and columns past the
+// matrix edge read the last row (their results are discarded).
+constexpr int kBM2 = 256, kBN2 = 256, kBK2 = 64;
+constexpr int kStage2 = (kBM2 + kBN2) * kBK2;   // bf16 values per LDS stage
+
+__device__ inline int chunk_swizzle(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
     const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
-    int tiles_m, int tiles_n, int vec) {
+    int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) uint16_t smem[2 * kStage2];
 
   int tm, tn, split;
@@ -521,23 +534,26 @@ __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3, lr = lane & 31, lh = lane >> 5;
 
-  uint4 ra[4], rb[4];
-  auto gload = [&](int64_t k0) {
+  // Loader: each wavefront moves 4 blocks of 8 rows of A and of B per K
+  // step; block q's lane l carries row 8 q + l / 8, stored chunk l % 8,
+  // which holds logical chunk (l % 8) ^ f(row).
+  const uint16_t *srcA[4], *srcB[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int id = tid + 512 * i, r = id >> 3, c = (id & 7) * 8;
-      ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
-      rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
-    }
-  };
-  auto lstore = [&](int buf) {
+  for (int i = 0; i < 4; ++i) {
+    const int q = wave * 4 + i, r = q * 8 + (lane >> 3);
+    const int lc = (lane & 7) ^ chunk_swizzle(r);
+    const int64_t ga = min(row0 + r, M - 1), gb = min(col0 + r, N - 1);
+    srcA[i] = S + ga * P + lc * 8;
+    srcB[i] = D + gb * P + lc * 8;
+  }
+  auto issue = [&](int64_t k0, int buf) {
     uint16_t *As = smem + buf * kStage2;
-    uint16_t *Bs = As + kBM2 * kLd2;
+    uint16_t *Bs = As + kBM2 * kBK2;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int id = tid + 512 * i, r = id >> 3, c = (id & 7) * 8;
-      *reinterpret_cast<uint4 *>(&As[r * kLd2 + c]) = ra[i];
-      *reinterpret_cast<uint4 *>(&Bs[r * kLd2 + c]) = rb[i];
+      const int q = wave * 4 + i;
+      __builtin_amdgcn_global_load_lds(srcA[i] + k0, (__attribute__((address_space(3))) void *)(As + q * 512), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(srcB[i] + k0, (__attribute__((address_space(3))) void *)(Bs + q * 512), 16, 0, 0);
     }
   };
 
@@ -549,31 +565,52 @@ __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int64_t steps = (P + kBK2 - 1) / kBK2;
-  gload(0);
-  lstore(0);
+  // fragment rows share lr's swizzle: logical chunk 2 kk + lh sits at
+  // 2 (kk ^ (f >> 1)) + ((lh ^ f) & 1)
+  const int fl = chunk_swizzle(lr), fhi = fl >> 1, flo = (lh ^ fl) & 1;
+  const int arow = (wm * 128 + lr) * kBK2, brow = (wn * 64 + lr) * kBK2;
+  bf16x8 fa[2][4], fb[2][2];
+  auto frags = [&](const uint16_t *As, const uint16_t *Bs, int kk, int slot) {
+    const int c = (2 * (kk ^ fhi) + flo) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      fa[slot][i] = *reinterpret_cast<const bf16x8 *>(&As[arow + i * 32 * kBK2 + c]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      fb[slot][j] = *reinterpret_cast<const bf16x8 *>(&Bs[brow + j * 32 * kBK2 + c]);
+  };
+
+  const int64_t steps = P / kBK2;
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wavefront's loads are in LDS
   __syncthreads();
   for (int64_t st = 0; st < steps; ++st) {
     const int buf = (int)(st & 1);
-    if (st + 1 < steps) gload((st + 1) * kBK2);
+    if (st + 1 < steps) issue((st + 1) * kBK2, buf ^ 1);
     const uint16_t *As = smem + buf * kStage2;
-    const uint16_t *Bs = As + kBM2 * kLd2;
+    const uint16_t *Bs = As + kBM2 * kBK2;
+    frags(As, Bs, 0, 0);
 #pragma unroll
     for (int kk = 0; kk < kBK2 / 16; ++kk) {
-      bf16x8 a[4], b[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 128 + i * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 64 + j * 32 + lr) * kLd2 + kk * 16 + lh * 8]);
+      // the scheduling barriers keep the next slice's reads ahead of this
+      // slice's MFMAs (the compiler would otherwise sink them to save
+      // registers and stall every MFMA group on a fresh LDS read)
+      if (kk + 1 < kBK2 / 16) {
+        frags(As, Bs, kk + 1, (kk + 1) & 1);
+        // LDS reads complete in order: this slice's 6 are in once at most
+        // the next slice's 6 are outstanding
+        __builtin_amdgcn_s_waitcnt(0xC67F);   // lgkmcnt(6), vmcnt/expcnt not waited
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[kk & 1][i], fb[kk & 1][j],
+                                                              acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (st + 1 < steps) lstore(buf ^ 1);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __syncthreads();
   }
 
@@ -636,12 +673,12 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
                        dn, M, N, P, cand, tiles_m, tiles_n, vec);
     return hipGetLastError();
   }
-  if (match_bf16_tile_rows(M, N, false) == 256) {
+  if (match_bf16_tile_rows(M, N, P, S, D, false) == 256) {
     const int tiles_m = (int)((M + kBM2 - 1) / kBM2), tiles_n = (int)((N + kBN2 - 1) / kBN2);
     const int64_t blocks = (int64_t)tiles_m * tiles_n;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(match_bf16_big_kernel, dim3((unsigned)blocks), dim3(512), 0, s, S, D, sn,
-                       dn, M, N, P, cand, tiles_m, tiles_n, vec);
+                       dn, M, N, P, cand, tiles_m, tiles_n);
     return hipGetLastError();
   }
   const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
@@ -742,10 +779,10 @@ __global__ __launch_bounds__(256) void rescore_kernel(
   }
 }
 
-hipError_t launch_rescore(const uint32_t *cand, int64_t M, int64_t N, int64_t P, int64_t m_offset,
-                          const float *S32, const float *D32, const float *sn, const float *dn,
-                          int32_t *best_idx, float *best_dist, bool x3, hipStream_t s) {
-  const int tr = match_bf16_tile_rows(M, N, x3);
+hipError_t launch_rescore(const uint32_t *cand, int tile_rows, int64_t M, int64_t N, int64_t P,
+                          int64_t m_offset, const float *S32, const float *D32, const float *sn,
+                          const float *dn, int32_t *best_idx, float *best_dist, hipStream_t s) {
+  const int tr = tile_rows;
   const int tiles_m = (int)((M + tr - 1) / tr);
   const int vec = (P % 4 == 0) && al16(S32) && al16(D32);
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, cand, tiles_m,

@@ -157,27 +157,8 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
     mn[d] = valid ? l0[d] : 0x7fffffff;
     mx[d] = valid ? l0[d] : -0x7fffffff;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off));
-    }
-  if (lane == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      red[wave][d] = mn[d];
-      red[wave][3 + d] = mx[d];
-    }
-  }
   if (tid < 66) cnt[tid] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    mn[d] = min(min(red[0][d], red[1][d]), min(red[2][d], red[3][d]));
-    mx[d] = max(max(red[0][3 + d], red[1][3 + d]), max(red[2][3 + d], red[3][3 + d]));
-  }
+  block_minmax3(mn, mx, red);
   if (!(mn[0] <= mx[0])) return;  // no valid point in the block (uniform)
   const int e0 = mx[0] - mn[0] + W, e1 = mx[1] - mn[1] + W, e2 = mx[2] - mn[2] + W;
   float w0[W], w1[W], w2[W];

@@ -189,17 +189,33 @@ def test_bf16_chunked_streaming():
     assert np.all(ex[b[0], cols] <= ex[a[0], cols] + E[b[0], cols] + E[a[0], cols])
 
 
-def test_bf16_large_tile_kernel_against_oracle_on_sampled_images():
-    """8,192 x 8,192 fills >= 4 rounds of 256 x 256 tiles (large-tile BF16
-    kernel); a ragged P of 136 exercises the scalar loads.  The oracle
-    checks 192 sampled images exactly."""
+@pytest.mark.parametrize("M,N,P,misalign", [
+    (8192, 8192, 192, False),   # 256 x 256 tiles, all full
+    (8300, 8150, 192, False),   # 256 x 256 tiles with ragged edge tiles
+    (8192, 8192, 136, False),   # P not a multiple of 64: 128 x 128 tiles
+    (8192, 8192, 192, True),    # operands not 16-byte aligned: 128 x 128 tiles
+])
+def test_bf16_large_shapes_against_oracle_on_sampled_images(M, N, P, misalign):
+    """Shapes that fill >= 4 rounds of 256 x 256 tiles: the large-tile BF16
+    kernel when P is a whole number of its K steps and the operands are
+    16-byte aligned, else the 128-row kernel.  The oracle checks 192 sampled
+    images exactly."""
     g = np.random.default_rng(11)
-    M, N, P = 8192, 8192, 136
     base = g.gamma(2.0, 10.0, (M, P)).astype(np.float32)
     pick = g.integers(0, M, N)
     D = g.poisson(base[pick]).astype(np.float32)
-    assert spfel.match_workspace_bytes(M, N, P, spfel.MATCH_BF16_RESCORE8) == (M // 256) * N * 32
-    ib, db = run_bf16(base, D)
+    assert spfel.match_workspace_bytes(M, N, P, spfel.MATCH_BF16_RESCORE8) == -(-M // 128) * N * 32
+    St, Dt = gpu(base), gpu(D)
+    if misalign:   # views one element into a larger buffer
+        Sb = torch.empty(M * P + 8, dtype=torch.bfloat16, device=DEV)[1:1 + M * P].view(M, P)
+        Sb.copy_(St)
+    else:
+        Sb = St.to(torch.bfloat16)
+    Db = Dt.to(torch.bfloat16)
+    bi, bd = spfel.new_best(N, DEV)
+    spfel.match(Sb, spfel.row_norm2(St), Db, spfel.row_norm2(Dt), bi, bd,
+                mode=spfel.MATCH_BF16_RESCORE8, slices_f32=St, images_f32=Dt)
+    ib, db = host(bi), host(bd)
     cols = np.sort(g.choice(N, 192, replace=False))
     S64, Ds = base.astype(np.float64), D[cols].astype(np.float64)
     ex = om.distances_expanded(S64, Ds)
