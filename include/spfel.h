@@ -30,6 +30,9 @@
  *     4-byte aligned (8-byte for complex64, 16-byte preferred).
  *   Streams: `stream` is a hipStream_t (NULL = default stream).  Every call
  *     only enqueues work on it and returns; nothing synchronises the device.
+ *     Calls on one plan share its device buffers (fine grid, accumulator,
+ *     rotation table): work they enqueue on different streams must not
+ *     overlap.
  *   Errors: every call returns an spfel_status; on failure nothing has been
  *     enqueued (validation runs before any launch) unless the status is
  *     SPFEL_EHIP, and spfel_last_error() describes the failure.  No C++

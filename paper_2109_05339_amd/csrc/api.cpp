@@ -164,8 +164,8 @@ static bool aligned(const void *p, size_t a) {
 }
 
 static void free_plan(Plan *p) {
-  void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials, p->det_sorted,
-                  p->det_perm};
+  void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials, p->rot,
+                  p->det_sorted, p->det_perm};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {p->ev_start, p->ev_sliced[0], p->ev_sliced[1], p->ev_matched[0],
@@ -242,7 +242,8 @@ int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
               {reinterpret_cast<void **>(&p->t1), tmp_b},
               {reinterpret_cast<void **>(&p->t2), tmp_b},
               {&p->acc, grid_b},
-              {reinterpret_cast<void **>(&p->partials), kMaxPartials * sizeof(double)}};
+              {reinterpret_cast<void **>(&p->partials), kMaxPartials * sizeof(double)},
+              {reinterpret_cast<void **>(&p->rot), kRotCap * 9 * sizeof(double)}};
   for (auto &r : reqs) {
     if (test_fail_alloc()) {
       free_plan(p);

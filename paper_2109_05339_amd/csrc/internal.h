@@ -35,6 +35,9 @@ struct Plan {
   void *acc = nullptr;
   // Per-block partial sums of the weighted-residual loss.
   double *partials = nullptr;
+  // Scaled rotations of up to kRotCap orientations of one slicing launch:
+  // rot[9 m + 3 d + e] = R(q_m)[d][e] n_f / (2 pi), float64.
+  double *rot = nullptr;
   // Registered detector template (spfel_set_detector): points sorted along
   // a Hilbert curve on their principal plane so that every run of kTile
   // consecutive points is a compact patch; det_perm maps a sorted position
@@ -54,6 +57,8 @@ struct Plan {
 
 // Points per detector tile of the tiled slicing/spreading kernels.
 constexpr int kTile = 256;
+// Orientations per slicing launch (size of Plan::rot).
+constexpr int64_t kRotCap = 65536;
 
 // Status helpers: set the thread-local message and return the code.
 int fail(int code, const std::string &msg);

@@ -8,25 +8,38 @@
 
 namespace spfel {
 
+// Scaled rotation of each orientation, rot[9 m + 3 d + e] =
+// R(q_m)[d][e] n_f / (2 pi) in float64, computed once per orientation for
+// all of its points; a zero or non-finite quaternion stores NaN.
+__global__ __launch_bounds__(256) void rotation_kernel(const float *__restrict__ quats, int64_t M,
+                                                       double scale, double *__restrict__ rot) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double R[9];
+  const bool ok = quat_rot(quats + 4 * m, R);
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) rot[9 * m + k] = ok ? R[k] * scale : nan;
+}
+
 template <int W, bool CPLX>
 __global__ __launch_bounds__(256) void interp_gather_kernel(
-    const void *__restrict__ u_, int nf, float beta, const float *__restrict__ quats, int64_t M,
+    const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
     const float *__restrict__ detq, int64_t P, void *__restrict__ out_,
     uint16_t *__restrict__ out_bf16) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * P) return;
   const int64_t m = idx / P;
   const int64_t p = idx - m * P;
-  double R[9];
-  bool ok = quat_rot(quats + 4 * m, R);
+  const double *R = rot + 9 * m;
+  bool ok = R[0] == R[0];
   const double q0 = detq[3 * p], q1 = detq[3 * p + 1], q2 = detq[3 * p + 2];
-  const double scale = (double)nf / (2.0 * M_PI);
   int base[3];
   float frac[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double x = R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2;
-    ok = ok && support_split<W>(x * scale, nf, base[d], frac[d]);
+    const double t = R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2;
+    ok = ok && support_split<W>(t, nf, base[d], frac[d]);
   }
   if (!ok) {
     const float nan = __uint_as_float(0x7fc00000u);
@@ -117,11 +130,10 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
 template <bool CPLX>
 constexpr int brick_bytes() { return CPLX ? 65536 : 32768; }
 
-// LDS banks (4 bytes wide) and the number of candidate brick layouts.
-#ifndef SPFEL_LDS_BANKS
-#define SPFEL_LDS_BANKS 64
-#endif
-constexpr int kBanks = SPFEL_LDS_BANKS;
+// The LDS serves 128 bytes per cycle: a wavefront's reads of T cells go
+// through in passes of 128 / sizeof(T) lanes, and bank conflicts arise
+// among the lanes of one pass.  kLayouts candidate brick layouts are scored
+// per block.
 constexpr int kLayouts = 16;
 
 __device__ inline int wrap_mod(int v, int n) {
@@ -131,7 +143,7 @@ __device__ inline int wrap_mod(int v, int n) {
 
 template <int W, bool CPLX>
 __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
-    const void *__restrict__ u_, int nf, float beta, const float *__restrict__ quats, int64_t M,
+    const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     void *__restrict__ out_, uint16_t *__restrict__ out_bf16) {
   typedef typename std::conditional<CPLX, float2, float>::type T;
@@ -146,9 +158,8 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   const int tile = vb - (int)m * tiles;
   const int64_t i = (int64_t)tile * kTile + threadIdx.x;
   const bool inb = i < P;
-  double R[9];
-  const bool qok = quat_rot(quats + 4 * m, R);
-  const double scale = (double)nf / (2.0 * M_PI);
+  const double *R = rot + 9 * m;   // block-uniform: scalar loads
+  const bool qok = R[0] == R[0];
   int l0[3] = {0, 0, 0};
   float frac[3] = {0.f, 0.f, 0.f};
   bool valid = inb && qok;
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
     const double q0 = dets[3 * i], q1 = dets[3 * i + 1], q2 = dets[3 * i + 2];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double t = (R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2) * scale;
+      const double t = R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2;
       if (!(fabs(t) < 1e8)) {
         valid = false;
       } else {
@@ -178,21 +189,21 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   // Brick layout: cell (x0, x1, x2) at x0 * s0 + x1 * p2 + x2, with the row
   // pitch p2 >= p4 (e2 rounded up to whole 16-byte segments, so a segment
   // store never spills into the next row) and the plane stride
-  // s0 >= e1 * p2.  For real cells the small paddings are chosen per block:
-  // a wavefront's 64 lanes read 64 cells at a common offset from their
-  // support origins, so the LDS bank conflicts of every gather read are
-  // those of the lanes' origin addresses.  The first wavefront scores each
-  // candidate layout by letting every lane write its origin address into a
-  // table slot named by the address's bank and read the slot back: a lane
-  // that finds another address there shares its bank with a different
-  // cell.  The candidate with the fewest such lanes wins (ties: the first);
-  // the other wavefronts' patches lie next to the first's, under the same
-  // rotation, and share its choice.
+  // s0 >= e1 * p2.  The small paddings are chosen per block: a wavefront's
+  // 64 lanes read 64 cells at a common offset from their support origins,
+  // so the LDS bank conflicts of every gather read are those of the lanes'
+  // origin addresses.  The first wavefront scores each candidate layout by
+  // letting every lane write its origin address into a table slot named by
+  // the address's bank group (one table per LDS pass of lanes) and read the
+  // slot back: a lane that finds another address there shares its banks
+  // with a different cell in its pass.  The candidate with the fewest such
+  // lanes wins (ties: the first); the other wavefronts' patches lie next to
+  // the first's, under the same rotation, and share its choice.
   constexpr int kVec = 16 / (int)sizeof(T);
   const int nseg = (e2 + kVec - 1) / kVec;
   const int p4 = nseg * kVec;
   const bool use_lds = any && e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * p4 <= kCap;
-  const bool choose = !CPLX && use_lds && e0 * (e1 * (p4 + 3) + 3) <= kCap;
+  const bool choose = use_lds && e0 * (e1 * (p4 + 3) + 3) <= kCap;
   if (use_lds && threadIdx.x < 64) {
     // fine-grid offsets of every brick plane, row and column, wrapped once
     // per block (n_f <= 1022, so n_f^3 cells index in 32 bits)
@@ -204,7 +215,10 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
       // candidate c = 4 pe + d: p2 = p4 + pe, s0 = e1 p2 + d, so the origin
       // address is row * (p4 + pe) + d * x0 + x2 with row = x0 e1 + x1
       const int x0 = l0[0] - mn[0], row = x0 * e1 + (l0[1] - mn[1]);
-      int *tab = reinterpret_cast<int *>(brick);   // kLayouts x (kBanks + 1) slots
+      // a table per candidate and pass of kPass lanes, one slot per bank
+      // group (cell address mod kPass) plus one for invalid lanes
+      constexpr int kPass = 128 / (int)sizeof(T), kPasses = 64 / kPass;
+      int *tab = reinterpret_cast<int *>(brick) + (t / kPass) * (kPass + 1);
       int addr[kLayouts], slot[kLayouts];
       int a_pe = row * p4 + (l0[2] - mn[2]);
 #pragma unroll
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
         for (int d = 0; d < 4; ++d) {
           const int c = 4 * pe + d;
           addr[c] = a;
-          slot[c] = c * (kBanks + 1) + (valid ? (a & (kBanks - 1)) : kBanks);
+          slot[c] = kPasses * c * (kPass + 1) + (valid ? (a & (kPass - 1)) : kPass);
           tab[slot[c]] = a;
           a += x0;
         }
@@ -399,7 +413,7 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
 }
 
 template <int W>
-static hipError_t interp_w(const Plan &pl, const float *quats, int64_t M, const float *detq,
+static hipError_t interp_w(const Plan &pl, const double *rot, int64_t M, const float *detq,
                            int64_t P, void *out, uint16_t *out_bf16, hipStream_t s) {
   const bool cplx = pl.domain == SPFEL_COMPLEX;
   if (detq == nullptr) {
@@ -408,11 +422,11 @@ static hipError_t interp_w(const Plan &pl, const float *quats, int64_t M, const 
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (cplx)
       hipLaunchKernelGGL((interp_tiled_kernel<W, true>), dim3((unsigned)blocks), dim3(kTile), 0, s,
-                         pl.u, pl.nf, (float)pl.beta, quats, M, pl.det_sorted, pl.det_perm, P,
+                         pl.u, pl.nf, (float)pl.beta, rot, M, pl.det_sorted, pl.det_perm, P,
                          tiles, out, out_bf16);
     else
       hipLaunchKernelGGL((interp_tiled_kernel<W, false>), dim3((unsigned)blocks), dim3(kTile), 0,
-                         s, pl.u, pl.nf, (float)pl.beta, quats, M, pl.det_sorted, pl.det_perm, P,
+                         s, pl.u, pl.nf, (float)pl.beta, rot, M, pl.det_sorted, pl.det_perm, P,
                          tiles, out, out_bf16);
     return hipGetLastError();
   }
@@ -420,22 +434,37 @@ static hipError_t interp_w(const Plan &pl, const float *quats, int64_t M, const 
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
   if (cplx)
     hipLaunchKernelGGL((interp_gather_kernel<W, true>), grid, block, 0, s, pl.u, pl.nf,
-                       (float)pl.beta, quats, M, detq, P, out, out_bf16);
+                       (float)pl.beta, rot, M, detq, P, out, out_bf16);
   else
     hipLaunchKernelGGL((interp_gather_kernel<W, false>), grid, block, 0, s, pl.u, pl.nf,
-                       (float)pl.beta, quats, M, detq, P, out, out_bf16);
+                       (float)pl.beta, rot, M, detq, P, out, out_bf16);
   return hipGetLastError();
 }
 
+// Orientations go in batches of kRotCap: each batch's scaled rotations are
+// computed into the plan's table, then its points are interpolated.
 hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M, const float *detq,
                          int64_t P, void *out, uint16_t *out_bf16, hipStream_t s) {
-  switch (pl.w) {
-    case 4: return interp_w<4>(pl, quats, M, detq, P, out, out_bf16, s);
-    case 5: return interp_w<5>(pl, quats, M, detq, P, out, out_bf16, s);
-    case 6: return interp_w<6>(pl, quats, M, detq, P, out, out_bf16, s);
-    case 7: return interp_w<7>(pl, quats, M, detq, P, out, out_bf16, s);
-    default: return interp_w<8>(pl, quats, M, detq, P, out, out_bf16, s);
+  const size_t el = pl.domain == SPFEL_COMPLEX ? 8 : 4;
+  const double scale = (double)pl.nf / (2.0 * M_PI);
+  for (int64_t m0 = 0; m0 < M; m0 += kRotCap) {
+    const int64_t mc = M - m0 < kRotCap ? M - m0 : kRotCap;
+    hipLaunchKernelGGL(rotation_kernel, dim3((unsigned)((mc + 255) / 256)), dim3(256), 0, s,
+                       quats + 4 * m0, mc, scale, pl.rot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void *o = out ? static_cast<char *>(out) + (size_t)m0 * P * el : nullptr;
+    uint16_t *ob = out_bf16 ? out_bf16 + (size_t)m0 * P : nullptr;
+    switch (pl.w) {
+      case 4: e = interp_w<4>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+      case 5: e = interp_w<5>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+      case 6: e = interp_w<6>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+      case 7: e = interp_w<7>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+      default: e = interp_w<8>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+    }
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 // Squared norm of each row: 256 threads take strided partial sums (one
