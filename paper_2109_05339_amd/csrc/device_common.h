@@ -85,18 +85,16 @@ __device__ inline float key_float(uint32_t k) {
 }
 
 // Minimum over the 64 lanes of a wavefront (all lanes active), returned to
-// every lane.  DPP row operations do the work on the vector ALU: two
-// quad-permute butterflies and the half/full row mirrors give each row of 16
-// lanes its minimum; broadcasts of lane 15 into rows 1 and 3, then of lane 31
-// into rows 2 and 3, leave the wavefront's minimum in lane 63.
+// every lane.  DPP row operations fused into the minimum (two quad-permute
+// butterflies, then the half and full row mirrors) give each row of 16
+// lanes its minimum; the four rows' results are then read out as scalars.
 __device__ inline int wave_min(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));  // row_mirror
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
-  return __builtin_amdgcn_readlane(v, 63);
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Block-wide minimum and maximum of three ints over a block of four
