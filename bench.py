@@ -55,11 +55,100 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one step of each path and a plain 1 GiB "
                          "device copy (the copy calibrates FETCH_SIZE/WRITE_SIZE), no timing")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs of --counters (FETCH_SIZE, then "
+                         "WRITE_SIZE) into profiles/traffic.json and exit (no GPU)")
     return ap.parse_args()
+
+
+# HBM traffic of the roofline kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (KiB per dispatch) scaled by what the same counters read for a
+# plain 1 GiB device copy; valid only while the kernel's sources hash to the
+# value recorded with the counters.
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2109_05339_amd", "csrc")
+KERNEL_SOURCES = {
+    "interp_tiled_kernel": ["interp.hip", "device_common.h", "internal.h"],
+    "match_f32_kernel": ["match.hip", "device_common.h", "internal.h"],
+}
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _pmc_dispatches(d: str, counter: str):
+    """(kernel name, grid size, KiB, dispatch id) of every dispatch in a
+    --pmc run."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]))
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return [(k[1], k[2], v, k[0]) for k, v in per.items()]
+
+
+def write_traffic(fetch_dir: str, write_dir: str) -> int:
+    out = {"method": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, over `bench.py "
+                     "--counters`; KiB per dispatch scaled by the counter's reading for a "
+                     "1 GiB device copy; per launch at the default workload",
+           "kernels": {}}
+    fetch, write = _pmc_dispatches(fetch_dir, "FETCH_SIZE"), _pmc_dispatches(write_dir, "WRITE_SIZE")
+
+    def largest(rows, pred):
+        rows = [r for r in rows if pred(r[0])]
+        return max(rows, key=lambda r: r[1]) if rows else None
+
+    # the calibration copy is the run's last dispatch
+    cf, cw = max(fetch, key=lambda r: r[3]), max(write, key=lambda r: r[3])
+    if "copy" not in cf[0] or "copy" not in cw[0]:
+        cf = cw = None
+    if cf is None or cw is None:
+        print("no copy dispatch found for calibration", file=sys.stderr)
+        return 1
+    f_fac, w_fac = COPY_BYTES / (cf[2] * 1024.0), COPY_BYTES / (cw[2] * 1024.0)
+    out["calibration"] = {"copy_bytes": COPY_BYTES, "fetch_kib": cf[2], "write_kib": cw[2],
+                          "fetch_factor": f_fac, "write_factor": w_fac}
+    for k in KERNEL_SOURCES:
+        a, b = largest(fetch, lambda n: k in n), largest(write, lambda n: k in n)
+        if a is None or b is None:
+            continue
+        fb, wb = a[2] * 1024.0 * f_fac, b[2] * 1024.0 * w_fac
+        out["kernels"][k] = {"source_sha256": kernel_source_hash(k), "grid_size": a[1],
+                             "fetch_kib": a[2], "write_kib": b[2], "fetch_bytes": fb,
+                             "write_bytes": wb, "bytes_per_launch": fb + wb}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+def traffic_of(kernel: str):
+    """HBM bytes per launch of `kernel`, or None if not measured for the
+    current sources."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            rec = json.load(fh)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["bytes_per_launch"] if rec["source_sha256"] == kernel_source_hash(kernel) else None
 
 
 def main() -> int:
     args = parse()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one "
               "GPU and the multi-GPU form of this path is a design, not a build", file=sys.stderr)
@@ -191,10 +280,12 @@ def main() -> int:
     log(f"fp32 step {ms_per_step:.3f} ms; unpipelined slice {slice_ms:.3f} ms, match {match_ms:.3f} ms")
     roof_match = {"kernel": "match_f32_kernel", "bound": "mfma", "achieved": gemm_tf,
                   "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                  "frac": gemm_tf / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
+                  "frac": gemm_tf / PEAK_FP32_MFMA_TFLOPS,
+                  "traffic": traffic_of("match_f32_kernel")}
     roof_interp = {"kernel": "interp_tiled_kernel", "bound": "alu", "achieved": interp_tf,
                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                   "frac": interp_tf / PEAK_FP32_VECTOR_TFLOPS, "traffic": None}
+                   "frac": interp_tf / PEAK_FP32_VECTOR_TFLOPS,
+                   "traffic": traffic_of("interp_tiled_kernel")}
     dominant = roof_interp if slice_ms >= match_ms else roof_match
 
     out = {
