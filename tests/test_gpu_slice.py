@@ -203,3 +203,27 @@ def test_registered_scattered_points_use_the_global_fallback():
     assert rel(a, oracle_slices(model(1), q, det, real=True)) <= TOL
     with pytest.raises(ValueError):
         make_plan(N).slice(gpu(q))
+
+
+@pytest.mark.parametrize("registered", [False, True])
+def test_more_orientations_than_one_rotation_batch(registered):
+    """Orientations are sliced in batches of 65,536 (one table of scaled
+    rotations per batch): 65,536 + 300 orientations in one call equal the
+    two batches sliced in separate calls, bit for bit, and rows on both
+    sides of the batch boundary match the oracle."""
+    N, cap = 17, 65536
+    det = detector(8)                                  # 64 points
+    q = synth.quaternions(synth.config(1), "ref_quats", cap + 300)
+    m = synth.random_model(8, N)
+    plan = make_plan(N)
+    plan.set_model(gpu(m))
+    if registered:
+        plan.set_detector(gpu(det))
+    dq = None if registered else gpu(det)
+    qt = gpu(q)
+    whole = host(plan.slice(qt, dq)[0])
+    first = host(plan.slice(qt[:cap].contiguous(), dq)[0])
+    second = host(plan.slice(qt[cap:].contiguous(), dq)[0])
+    np.testing.assert_array_equal(whole, np.concatenate([first, second]))
+    rows = np.r_[0:2, cap - 2:cap + 2, cap + 298:cap + 300]
+    assert rel(whole[rows], oracle_slices(m, q[rows], det, real=True)) <= TOL
