@@ -6,6 +6,7 @@ import torch
 
 import synth
 import paper_2109_05339_amd as spfel
+from oracle import geometry, nufft
 from oracle import match as omatch
 from tests._common import DEV, rel, gpu, host, model, detector, f32, oracle_slices
 
@@ -227,3 +228,26 @@ def test_more_orientations_than_one_rotation_batch(registered):
     np.testing.assert_array_equal(whole, np.concatenate([first, second]))
     rows = np.r_[0:2, cap - 2:cap + 2, cap + 298:cap + 300]
     assert rel(whole[rows], oracle_slices(m, q[rows], det, real=True)) <= TOL
+
+
+@pytest.mark.parametrize("w,bw", [(4, 2.30), (5, 2.30), (7, 2.30), (8, 2.30), (6, 1.80)])
+def test_other_kernel_widths_and_shapes(w, bw):
+    """Every compiled kernel width, and a different ES shape, on both the
+    per-point and the tiled path, against the oracle with the same w, beta
+    and n_f (slices) and for the adjoint (merge)."""
+    N = 21
+    m = synth.random_model(9, N)
+    det = detector(16)
+    q = synth.quaternions(synth.config(1), "ref_quats", 6)
+    plan = spfel.Plan(N, kernel_width=w, beta_over_w=bw, device=DEV)
+    plan.set_model(gpu(m))
+    x = geometry.slice_points(f32(q), f32(det)).reshape(-1, 3)
+    ref = nufft.nufft2(m, x, w=w, beta_over_w=bw, real=True).reshape(len(q), -1)
+    a = host(plan.slice(gpu(q), gpu(det))[0])
+    assert rel(a, ref) <= TOL
+    plan.set_detector(gpu(det))
+    np.testing.assert_array_equal(host(plan.slice(gpu(q))[0]), a)
+    y = np.random.default_rng(w).standard_normal((len(q), len(det))).astype(np.float32)
+    out = host(plan.merge_adjoint(gpu(q), gpu(det), gpu(y)))
+    assert rel(out, nufft.nufft1(y.astype(np.float64).reshape(-1), x, N, w=w, beta_over_w=bw,
+                                 real=True)) <= TOL
