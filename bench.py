@@ -99,11 +99,11 @@ def _pmc_dispatches(d: str, counter: str):
     return [(k[1], k[2], v, k[0]) for k, v in per.items()]
 
 
-def write_traffic(fetch_dir: str, write_dir: str) -> int:
+def write_traffic(fetch_dir: str, write_dir: str, config: int) -> int:
     out = {"method": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, over `bench.py "
-                     "--counters`; KiB per dispatch scaled by the counter's reading for a "
-                     "1 GiB device copy; per launch at the default workload",
-           "kernels": {}}
+                     "--counters --config N`; KiB per dispatch scaled by the counter's "
+                     "reading for a 1 GiB device copy; per launch at workload N",
+           "config": config, "kernels": {}}
     fetch, write = _pmc_dispatches(fetch_dir, "FETCH_SIZE"), _pmc_dispatches(write_dir, "WRITE_SIZE")
 
     def largest(rows, pred):
@@ -134,12 +134,15 @@ def write_traffic(fetch_dir: str, write_dir: str) -> int:
     return 0
 
 
-def traffic_of(kernel: str):
+def traffic_of(kernel: str, config: int):
     """HBM bytes per launch of `kernel`, or None if not measured for the
-    current sources."""
+    current sources on this workload."""
     try:
         with open(TRAFFIC_JSON) as fh:
-            rec = json.load(fh)["kernels"][kernel]
+            data = json.load(fh)
+        rec = data["kernels"][kernel]
+        if data["config"] != config:
+            return None
     except (OSError, KeyError, ValueError):
         return None
     return rec["bytes_per_launch"] if rec["source_sha256"] == kernel_source_hash(kernel) else None
@@ -148,7 +151,7 @@ def traffic_of(kernel: str):
 def main() -> int:
     args = parse()
     if args.write_traffic:
-        return write_traffic(*args.write_traffic)
+        return write_traffic(*args.write_traffic, args.config)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one "
               "GPU and the multi-GPU form of this path is a design, not a build", file=sys.stderr)
@@ -281,11 +284,11 @@ def main() -> int:
     roof_match = {"kernel": "match_f32_kernel", "bound": "mfma", "achieved": gemm_tf,
                   "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                   "frac": gemm_tf / PEAK_FP32_MFMA_TFLOPS,
-                  "traffic": traffic_of("match_f32_kernel")}
+                  "traffic": traffic_of("match_f32_kernel", args.config)}
     roof_interp = {"kernel": "interp_tiled_kernel", "bound": "alu", "achieved": interp_tf,
                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                    "frac": interp_tf / PEAK_FP32_VECTOR_TFLOPS,
-                   "traffic": traffic_of("interp_tiled_kernel")}
+                   "traffic": traffic_of("interp_tiled_kernel", args.config)}
     dominant = roof_interp if slice_ms >= match_ms else roof_match
 
     out = {
