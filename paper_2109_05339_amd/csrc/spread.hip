@@ -104,9 +104,13 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
     float *__restrict__ acc, int nf, float beta, const float *__restrict__ quats, int64_t n_img,
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     const void *__restrict__ values_, const float *__restrict__ weights) {
-  __shared__ int pl[3][kTile];            // sorted points: support origin relative to the brick
-  __shared__ float py[2][kTile];          // value (re, im) times weight
-  __shared__ float pw[kTile][3 * W + 1];  // ES weights of the three axes (padded row)
+  // sorted points (slot kTile: a point of zero weights that pads the last
+  // product step): support origin relative to the brick, one byte per axis;
+  // axis-0 weights times the value (re, im); axis-1 and axis-2 weights
+  __shared__ int pk[kTile + 1];
+  __shared__ float pa[CPLX ? 2 : 1][kTile + 1][W];
+  __shared__ float pb[kTile + 1][W];
+  __shared__ float pc[kTile + 1][W];
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];
   __shared__ int cnt[66];                 // points per axis-1 cell, then exclusive offsets
@@ -209,16 +213,29 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
   __syncthreads();
   if (valid) {
     const int slot = atomicAdd(&cnt[k1], 1);   // cnt[k1] runs up to the old cnt[k1 + 1]
-    pl[0][slot] = l0[0] - mn[0];
-    pl[1][slot] = k1;
-    pl[2][slot] = l0[2] - mn[2];
-    py[0][slot] = yr;
-    py[1][slot] = yi;
+    pk[slot] = (l0[0] - mn[0]) | (k1 << 8) | ((l0[2] - mn[2]) << 16);
 #pragma unroll
     for (int a = 0; a < W; ++a) {
-      pw[slot][a] = w0[a];
-      pw[slot][W + a] = w1[a];
-      pw[slot][2 * W + a] = w2[a];
+      pa[0][slot][a] = w0[a] * yr;
+      if (CPLX) pa[CPLX ? 1 : 0][slot][a] = w0[a] * yi;
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      pb[slot][b] = w1[b];
+      pc[slot][b] = w2[b];
+    }
+  }
+  if (tid == 0) {
+    pk[kTile] = 0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      pa[0][kTile][a] = 0.f;
+      if (CPLX) pa[CPLX ? 1 : 0][kTile][a] = 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      pb[kTile][b] = 0.f;
+      pc[kTile][b] = 0.f;
     }
   }
   __syncthreads();
@@ -232,8 +249,10 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
   for (int job = wave; job < mblocks * nblocks; job += 4) {
     const int mb = job / nblocks, nb = job - mb * nblocks;
     const int ncell = nb * 32 + lr;
-    const int j1 = (int)(((float)ncell + 0.5f) * inv_e2);
-    const int j2 = ncell - j1 * e2;
+    const int j1c = (int)(((float)ncell + 0.5f) * inv_e2);
+    const int j2 = ncell - j1c * e2;
+    // columns past the brick take an axis-1 cell no point reaches
+    const int j1 = ncell < ncol ? j1c : 1024;
     const int i0 = mb * 32 + lr;
     // points whose axis-1 support meets rows [r_lo, r_hi] of this block
     const int r_lo = (nb * 32) / e2, r_hi = min(e1 - 1, (nb * 32 + 31) / e2);
@@ -247,20 +266,19 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
       acci[r] = 0.f;
     }
     for (int k0 = k_beg; k0 < k_end; k0 += 2) {
-      const int p = k0 + lh;
-      float a_r = 0.f, a_i = 0.f, b = 0.f;
-      if (p < k_end) {
-        const int da = i0 - pl[0][p], db = j1 - pl[1][p], dc = j2 - pl[2][p];
-        const bool ia = da >= 0 && da < W;
-        const bool ib = db >= 0 && db < W && dc >= 0 && dc < W && ncell < ncol;
-        const float wa = pw[p][ia ? da : 0];
-        const float wb = pw[p][W + (ib ? db : 0)] * pw[p][2 * W + (ib ? dc : 0)];
-        a_r = ia ? wa * py[0][p] : 0.f;
-        if (CPLX) a_i = ia ? wa * py[1][p] : 0.f;
-        b = ib ? wb : 0.f;
+      const int p = k0 + lh < k_end ? k0 + lh : kTile;
+      const int o = pk[p];
+      const unsigned da = (unsigned)(i0 - (o & 255));
+      const unsigned db = (unsigned)(j1 - ((o >> 8) & 255)), dc = (unsigned)(j2 - (o >> 16));
+      const bool ia = da < (unsigned)W, ib = db < (unsigned)W && dc < (unsigned)W;
+      const float a_r = pa[0][p][ia ? da : 0];
+      const float wb = pb[p][ib ? db : 0] * pc[p][ib ? dc : 0];
+      const float b = ib ? wb : 0.f;
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(ia ? a_r : 0.f, b, accr, 0, 0, 0);
+      if (CPLX) {
+        const float a_i = pa[CPLX ? 1 : 0][p][ia ? da : 0];
+        acci = __builtin_amdgcn_mfma_f32_32x32x2f32(ia ? a_i : 0.f, b, acci, 0, 0, 0);
       }
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a_r, b, accr, 0, 0, 0);
-      if (CPLX) acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a_i, b, acci, 0, 0, 0);
     }
     if (ncell < ncol) {
       const int64_t colg = (int64_t)wrap[1][j1] * nf + wrap[2][j2];
