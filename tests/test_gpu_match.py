@@ -11,7 +11,7 @@ import torch
 import synth
 import paper_2109_05339_amd as spfel
 from oracle import match as om
-from tests._common import DEV, gpu, host, model, detector
+from tests._common import DEV, gpu, host, detector, molecule_slices
 
 pytestmark = pytest.mark.gpu
 
@@ -26,17 +26,14 @@ def chain_rescore(P):
 
 @functools.lru_cache(maxsize=None)
 def c1_data(n_refs=1000, n_img=300):
-    """C1-shaped matcher inputs: slices of the C1 model at reference
-    orientations and Poisson images at random orientations (GPU-rendered;
-    they are only inputs here: both sides read the same float32 values)."""
+    """C1-shaped matcher inputs: the molecule's intensity at the reference
+    orientations and Poisson images of it at random orientations, made
+    without the library (both sides read the same float32 values)."""
     cfg = synth.config(1)
-    plan = spfel.Plan(cfg.n_model, device=DEV)
-    plan.set_model(gpu(model(1)))
-    det = gpu(detector(cfg.n_det))
-    lam0 = host(plan.slice(gpu(synth.quaternions(cfg, "image_quats", n_img)), det)[0])
-    lam0 = np.maximum(lam0, 0)
+    det = detector(cfg.n_det)
+    lam0 = host(molecule_slices(1, synth.quaternions(cfg, "image_quats", n_img), det))
     alpha = synth.photon_scale(lam0, cfg.photons)
-    S = alpha * host(plan.slice(gpu(synth.quaternions(cfg, "ref_quats", n_refs)), det)[0])
+    S = alpha * host(molecule_slices(1, synth.quaternions(cfg, "ref_quats", n_refs), det))
     D = synth.poisson_counts(cfg, alpha * lam0)
     return S.astype(np.float32), D.astype(np.float32)
 
@@ -231,3 +228,46 @@ def test_bf16_large_shapes_against_oracle_on_sampled_images(M, N, P, misalign):
     assert ok.mean() >= 0.9
     np.testing.assert_array_equal(ib[cols][ok], m1[ok])
     assert np.all(np.abs(db[cols] - ex[ib[cols], c]) <= 2 * E[ib[cols], c])
+
+
+@pytest.mark.parametrize("mode,M,N,P", [
+    (spfel.MATCH_FP32, 10000, 2048, 16384),            # the default workload's launch
+    (spfel.MATCH_BF16_RESCORE8, 8192, 16384, 65536),   # one chunk of workload 5
+])
+def test_full_size_launches_against_oracle_on_sampled_images(mode, M, N, P):
+    """The launches bench.py times, at their full sizes: slice rows uniform
+    in [0, 40) and Poisson images of randomly picked rows (seeded, made on
+    the device with torch).  The oracle's float64 distances of 24 sampled
+    images to every row decide the argmin and bound the returned distance."""
+    g = torch.Generator(device=DEV).manual_seed(17)
+    St = torch.rand((M, P), generator=g, device=DEV) * 40.0
+    pick = torch.randint(0, M, (N,), generator=g, device=DEV)
+    Dt = torch.poisson(St[pick], generator=g)
+    sn, dn = spfel.row_norm2(St), spfel.row_norm2(Dt)
+    bi, bd = spfel.new_best(N, DEV)
+    if mode == spfel.MATCH_FP32:
+        spfel.match(St, sn, Dt, dn, bi, bd)
+        L = chain_fp32(P)
+    else:
+        spfel.match(St.to(torch.bfloat16), sn, Dt.to(torch.bfloat16), dn, bi, bd, mode=mode,
+                    slices_f32=St, images_f32=Dt)
+        L = chain_rescore(P)
+    ib, db = host(bi), host(bd)
+    cols = np.sort(np.random.default_rng(3).choice(N, 24, replace=False))
+    Ds = host(Dt[torch.as_tensor(cols, device=DEV)]).astype(np.float64)
+    ex = np.empty((M, len(cols)))
+    E = np.empty((M, len(cols)))
+    dn2 = (Ds ** 2).sum(1)[None, :]
+    for r0 in range(0, M, 1024):       # float64 rows, a block at a time
+        S64 = host(St[r0:r0 + 1024]).astype(np.float64)
+        sn2 = (S64 ** 2).sum(1)[:, None]
+        ex[r0:r0 + 1024] = om.distances_expanded(S64, Ds)
+        E[r0:r0 + 1024] = om.fp32_distance_bound(sn2, dn2, S64 @ Ds.T, max(L, chain_fp32(P)))
+    c = np.arange(len(cols))
+    order = np.argsort(ex, axis=0, kind="stable")
+    m1, m2 = order[0], order[1]
+    decided = ex[m2, c] - ex[m1, c] > E[m1, c] + E[m2, c]
+    assert decided.all()
+    np.testing.assert_array_equal(ib[cols], m1)
+    np.testing.assert_array_equal(m1, host(pick)[cols])
+    assert np.all(np.abs(db[cols] - ex[m1, c]) <= 2 * E[m1, c])

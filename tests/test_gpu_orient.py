@@ -8,7 +8,7 @@ import torch
 
 import synth
 import paper_2109_05339_amd as spfel
-from tests._common import DEV, gpu, host, model, detector
+from tests._common import DEV, gpu, host, model, detector, molecule_slices
 
 pytestmark = pytest.mark.gpu
 
@@ -18,10 +18,9 @@ def inputs():
     cfg = synth.config(1)
     plan = spfel.Plan(cfg.n_model, device=DEV)
     plan.set_detector(gpu(detector(cfg.n_det)))
-    plan.set_model(gpu(model(1)))
-    lam = plan.slice(gpu(synth.quaternions(cfg, "image_quats", 300)))[0].clamp_(min=0)
-    alpha = synth.photon_scale(host(lam), cfg.photons)
-    images = gpu(synth.poisson_counts(cfg, alpha * host(lam)))
+    lam = host(molecule_slices(1, synth.quaternions(cfg, "image_quats", 300), detector(cfg.n_det)))
+    alpha = synth.photon_scale(lam, cfg.photons)
+    images = gpu(synth.poisson_counts(cfg, alpha * lam))
     plan.set_model(gpu(alpha * model(1)))
     return plan, gpu(synth.quaternions(cfg, "ref_quats", 1000)), images
 

@@ -2,6 +2,8 @@
 50,000 references, 2,048 images): the BF16 distance GEMM with per-image
 top-8 FP32 rescoring against the FP32 matcher on the same GPU and against
 float64 distances on a 512-image subset."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -9,22 +11,30 @@ import torch
 import synth
 import paper_2109_05339_amd as spfel
 from oracle import match as om
-from tests._common import DEV, gpu, host, model, detector
+from tests._common import DEV, gpu, host, detector, molecule_slices
 
 pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def c3_data():
+    """Workload-3 matcher inputs made without the library: the molecule's
+    intensity at the 50,000 reference orientations (scaled to the photon
+    mean) and Poisson images of it at 2,048 random orientations."""
+    cfg = synth.config(3)
+    det = detector(cfg.n_det)
+    lam0 = host(molecule_slices(3, synth.quaternions(cfg, "image_quats", cfg.n_images), det))
+    alpha = synth.photon_scale(lam0, cfg.photons)
+    images = gpu(synth.poisson_counts(cfg, alpha * lam0))
+    S = molecule_slices(3, synth.quaternions(cfg, "ref_quats", cfg.n_refs), det) * alpha
+    return S, images
 
 
 def test_c3_bf16_rescore_against_fp32_and_fp64():
     cfg = synth.config(3)
     M, n_img, P = cfg.n_refs, cfg.n_images, cfg.n_pix
-    plan = spfel.Plan(cfg.n_model, device=DEV)
-    plan.set_detector(gpu(detector(cfg.n_det)))
-    plan.set_model(gpu(model(3)))
-    lam0 = plan.slice(gpu(synth.quaternions(cfg, "image_quats", n_img)))[0].clamp_(min=0)
-    alpha = synth.photon_scale(host(lam0), cfg.photons)
-    images = gpu(synth.poisson_counts(cfg, alpha * host(lam0)))
-    plan.set_model(gpu(alpha * model(3)))
-    S, Sb, sn = plan.slice(gpu(synth.quaternions(cfg, "ref_quats", M)), bf16=True, norms=True)
+    S, images = c3_data()
+    Sb, sn = S.to(torch.bfloat16), spfel.row_norm2(S)
     dn = spfel.row_norm2(images)
     i32, d32 = spfel.new_best(n_img, DEV)
     spfel.match(S, sn, images, dn, i32, d32)
@@ -77,14 +87,8 @@ def test_c3_bf16x3_rescore_matches_fp32():
     every decided image of the 512-image subset and nearly all images."""
     cfg = synth.config(3)
     M, n_img, P = cfg.n_refs, cfg.n_images, cfg.n_pix
-    plan = spfel.Plan(cfg.n_model, device=DEV)
-    plan.set_detector(gpu(detector(cfg.n_det)))
-    plan.set_model(gpu(model(3)))
-    lam0 = plan.slice(gpu(synth.quaternions(cfg, "image_quats", n_img)))[0].clamp_(min=0)
-    alpha = synth.photon_scale(host(lam0), cfg.photons)
-    images = gpu(synth.poisson_counts(cfg, alpha * host(lam0)))
-    plan.set_model(gpu(alpha * model(3)))
-    S, _, sn = plan.slice(gpu(synth.quaternions(cfg, "ref_quats", M)), norms=True)
+    S, images = c3_data()
+    sn = spfel.row_norm2(S)
     dn = spfel.row_norm2(images)
     i32, _ = spfel.new_best(n_img, DEV)
     d32 = torch.full((n_img,), float("inf"), device=DEV)
