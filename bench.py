@@ -362,8 +362,7 @@ def main() -> int:
         log(f"merge_adjoint {t1:.3f} ms")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, alpha * m_host, images.cpu().numpy(),
-                                           args.cpu_sample, comps)
+        out["cpu_baseline"] = cpu_baseline(cfg, m_host, n_img, args.cpu_sample, comps)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -511,12 +510,16 @@ def bench_gradient(args, cfg, dev):
     return 0
 
 
-def cpu_baseline(cfg, model, images, n_sample, comps_total):
+def cpu_baseline(cfg, model, n_img, n_sample, comps_total):
     """The FP64 oracle on a bounded sample of the same step: the fine grid
     once, ``n_sample`` orientations sliced, and those slices matched against
-    every image; scaled to the full step's pixel-comparisons/s."""
+    ``n_img`` images; scaled to the full step's pixel-comparisons/s.  Its
+    inputs come from synth alone (the workload's model and seeded Poisson
+    images of the same shape and photon level; the values do not change the
+    oracle's running time)."""
     import synth
     from oracle import geometry, match, nufft
+    images = synth.poisson_counts(cfg, np.full((n_img, cfg.n_pix), float(cfg.photons)))
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
