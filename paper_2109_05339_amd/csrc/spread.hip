@@ -105,12 +105,14 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     const void *__restrict__ values_, const float *__restrict__ weights) {
   // sorted points (slot kTile: a point of zero weights that pads the last
-  // product step): support origin relative to the brick, one byte per axis;
-  // axis-0 weights times the value (re, im); axis-1 and axis-2 weights
+  // product step): support origin relative to the brick, one byte per axis,
+  // and a row of weights: axis-0 weights times the value (re; im), axis-1
+  // and axis-2 weights, each list followed by a zero so that an offset
+  // outside the support, clamped to W, reads 0
+  constexpr int kOA = 0, kOAI = W + 1, kOB = (CPLX ? 2 : 1) * (W + 1), kOC = kOB + W + 1;
+  constexpr int kRow = kOC + W + 1;
   __shared__ int pk[kTile + 1];
-  __shared__ float pa[CPLX ? 2 : 1][kTile + 1][W];
-  __shared__ float pb[kTile + 1][W];
-  __shared__ float pc[kTile + 1][W];
+  __shared__ float pw[kTile + 1][kRow];
   __shared__ int red[4][6];
   __shared__ int wrap[3][64];
   __shared__ int cnt[66];                 // points per axis-1 cell, then exclusive offsets
@@ -214,29 +216,23 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
   if (valid) {
     const int slot = atomicAdd(&cnt[k1], 1);   // cnt[k1] runs up to the old cnt[k1 + 1]
     pk[slot] = (l0[0] - mn[0]) | (k1 << 8) | ((l0[2] - mn[2]) << 16);
+    float *row = pw[slot];
 #pragma unroll
     for (int a = 0; a < W; ++a) {
-      pa[0][slot][a] = w0[a] * yr;
-      if (CPLX) pa[CPLX ? 1 : 0][slot][a] = w0[a] * yi;
+      row[kOA + a] = w0[a] * yr;
+      if (CPLX) row[kOAI + a] = w0[a] * yi;
+      row[kOB + a] = w1[a];
+      row[kOC + a] = w2[a];
     }
-#pragma unroll
-    for (int b = 0; b < W; ++b) {
-      pb[slot][b] = w1[b];
-      pc[slot][b] = w2[b];
-    }
+    row[kOA + W] = 0.f;
+    if (CPLX) row[kOAI + W] = 0.f;
+    row[kOB + W] = 0.f;
+    row[kOC + W] = 0.f;
   }
   if (tid == 0) {
     pk[kTile] = 0;
 #pragma unroll
-    for (int a = 0; a < W; ++a) {
-      pa[0][kTile][a] = 0.f;
-      if (CPLX) pa[CPLX ? 1 : 0][kTile][a] = 0.f;
-    }
-#pragma unroll
-    for (int b = 0; b < W; ++b) {
-      pb[kTile][b] = 0.f;
-      pc[kTile][b] = 0.f;
-    }
+    for (int e = 0; e < kRow; ++e) pw[kTile][e] = 0.f;
   }
   __syncthreads();
   // after the scatter, cnt[c] = points with cell <= c; the first point of
@@ -265,21 +261,24 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
       accr[r] = 0.f;
       acci[r] = 0.f;
     }
-    for (int k0 = k_beg; k0 < k_end; k0 += 2) {
-      const int p = k0 + lh < k_end ? k0 + lh : kTile;
+    // one product step: lane half lh supplies point p (offsets outside the
+    // support clamp to the zero entry W)
+    auto step = [&](int p) {
       const int o = pk[p];
-      const unsigned da = (unsigned)(i0 - (o & 255));
-      const unsigned db = (unsigned)(j1 - ((o >> 8) & 255)), dc = (unsigned)(j2 - (o >> 16));
-      const bool ia = da < (unsigned)W, ib = db < (unsigned)W && dc < (unsigned)W;
-      const float a_r = pa[0][p][ia ? da : 0];
-      const float wb = pb[p][ib ? db : 0] * pc[p][ib ? dc : 0];
-      const float b = ib ? wb : 0.f;
-      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(ia ? a_r : 0.f, b, accr, 0, 0, 0);
-      if (CPLX) {
-        const float a_i = pa[CPLX ? 1 : 0][p][ia ? da : 0];
-        acci = __builtin_amdgcn_mfma_f32_32x32x2f32(ia ? a_i : 0.f, b, acci, 0, 0, 0);
-      }
-    }
+      const unsigned da = min((unsigned)(i0 - (o & 255)), (unsigned)W);
+      const unsigned db = min((unsigned)(j1 - ((o >> 8) & 255)), (unsigned)W);
+      const unsigned dc = min((unsigned)(j2 - (o >> 16)), (unsigned)W);
+      const float *row = pw[p];
+      const float b = row[kOB + db] * row[kOC + dc];
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(row[kOA + da], b, accr, 0, 0, 0);
+      if (CPLX) acci = __builtin_amdgcn_mfma_f32_32x32x2f32(row[kOAI + da], b, acci, 0, 0, 0);
+    };
+    // the range is the same for the whole wavefront
+    const int kb = __builtin_amdgcn_readfirstlane(k_beg), ke = __builtin_amdgcn_readfirstlane(k_end);
+    int k0 = kb;
+#pragma unroll 2
+    for (; k0 + 2 <= ke; k0 += 2) step(k0 + lh);
+    if (k0 < ke) step(k0 + lh < ke ? k0 + lh : kTile);
     if (ncell < ncol) {
       const int64_t colg = (int64_t)wrap[1][j1] * nf + wrap[2][j2];
 #pragma unroll
