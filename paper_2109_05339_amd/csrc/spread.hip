@@ -276,7 +276,6 @@ __global__ __launch_bounds__(kTile) void spread_mfma_kernel(
     // the range is the same for the whole wavefront
     const int kb = __builtin_amdgcn_readfirstlane(k_beg), ke = __builtin_amdgcn_readfirstlane(k_end);
     int k0 = kb;
-#pragma unroll 2
     for (; k0 + 2 <= ke; k0 += 2) step(k0 + lh);
     if (k0 < ke) step(k0 + lh < ke ? k0 + lh : kTile);
     if (ncell < ncol) {
