@@ -521,14 +521,34 @@ constexpr int kStage2 = (kBM2 + kBN2) * kBK2;   // bf16 values per LDS stage
 
 __device__ inline int chunk_swizzle(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
+// Tile of a block of the large-tile kernel.  When the tile grid is a whole
+// number of 16 x 16 squares, each round of 256 resident blocks (one per CU)
+// covers one square: XCD x takes an 8 x 4 part of it (x % 2 selects the 8
+// m-tiles, x / 2 the 4 n-tiles), so a round reads 32 distinct tiles of S and
+// D instead of 40, each m-tile shared by four XCDs and each n-tile by two.
+// Other grids use the grouped order.
+__device__ inline void big_tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn) {
+  if ((tiles_m & 15) == 0 && (tiles_n & 15) == 0) {
+    const int bid = blockIdx.x, x = bid & 7, s = bid >> 3;
+    const int r = s >> 5, w = s & 31;
+    const int sq_m = tiles_m >> 4;
+    const int rm = r % sq_m, rn = r / sq_m;
+    tm = rm * 16 + (x & 1) * 8 + (w & 7);
+    tn = rn * 16 + (x >> 1) * 4 + (w >> 3);
+  } else {
+    int split;
+    tile_of_block(tiles_m, tiles_n, 1, tm, tn, split);
+  }
+}
+
 __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
     const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
     int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) uint16_t smem[2 * kStage2];
 
-  int tm, tn, split;
-  tile_of_block(tiles_m, tiles_n, 1, tm, tn, split);
+  int tm, tn;
+  big_tile_of_block(tiles_m, tiles_n, tm, tn);
   const int64_t row0 = (int64_t)tm * kBM2, col0 = (int64_t)tn * kBN2;
   // 8 wavefronts as 2 (M) x 4 (N), each owning a 128 x 64 block of the tile
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
