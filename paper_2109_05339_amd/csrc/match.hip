@@ -133,6 +133,9 @@ __global__ __launch_bounds__(kF32Threads) __attribute__((amdgpu_waves_per_eu(4, 
 #pragma unroll
       for (int r = 0; r < 16; ++r) part[i][r] = 0.f;
     const float *A = As[buf], *B = Bs[buf];
+    // raised priority for the MFMA section (the other wavefronts' loads and
+    // stores are served between its MFMAs, not ahead of them)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kk = 0; kk < kBK / 8; ++kk) {
       float4 a[2];
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(kF32Threads) __attribute__((amdgpu_waves_per_eu(4, 
         for (int i = 0; i < 2; ++i)
           part[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e], b[e], part[i], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int i = 0; i < 2; ++i) acc[i] += part[i];
     if (more) lstore(buf ^ 1);
@@ -622,12 +626,16 @@ __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
         __builtin_amdgcn_s_waitcnt(0xC67F);   // lgkmcnt(6), vmcnt/expcnt not waited
       }
       __builtin_amdgcn_sched_barrier(0);
+      // raised priority while issuing the MFMAs: the SIMD's other wavefront
+      // is then served between them, not ahead of them
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[kk & 1][i], fb[kk & 1][j],
                                                               acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
