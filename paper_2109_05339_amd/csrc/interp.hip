@@ -472,11 +472,32 @@ hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M, const fl
 // is fixed, so the result is deterministic.
 template <bool BF>
 __global__ __launch_bounds__(256) void row_norm2_kernel(const void *__restrict__ x_, int64_t cols,
-                                                        float *__restrict__ out) {
+                                                        float *__restrict__ out, int vec) {
   __shared__ float sh[256];
   const int64_t row = blockIdx.x;
   float acc = 0.f;
-  if (BF) {
+  if (vec) {
+    // 16-byte aligned rows of a whole number of 16-byte groups: each thread
+    // takes whole groups (8 bf16 or 4 float), in order
+    const uint4 *x = reinterpret_cast<const uint4 *>(static_cast<const char *>(x_) +
+                                                     row * cols * (BF ? 2 : 4));
+    const int64_t groups = cols / (BF ? 8 : 4);
+    for (int64_t g = threadIdx.x; g < groups; g += 256) {
+      const uint4 v = x[g];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (BF) {
+          const float lo = __uint_as_float(w[e] << 16), hi = __uint_as_float(w[e] & 0xffff0000u);
+          acc = fmaf(lo, lo, acc);
+          acc = fmaf(hi, hi, acc);
+        } else {
+          const float f = __uint_as_float(w[e]);
+          acc = fmaf(f, f, acc);
+        }
+      }
+    }
+  } else if (BF) {
     const uint16_t *x = static_cast<const uint16_t *>(x_) + row * cols;
     for (int64_t c = threadIdx.x; c < cols; c += 256) {
       const float v = bf16_to_f32(x[c]);
@@ -500,10 +521,11 @@ __global__ __launch_bounds__(256) void row_norm2_kernel(const void *__restrict__
 
 hipError_t launch_row_norm2(const void *x, bool bf16, int64_t rows, int64_t cols, float *out,
                             hipStream_t s) {
+  const int vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && cols % (bf16 ? 8 : 4) == 0;
   if (bf16)
-    hipLaunchKernelGGL((row_norm2_kernel<true>), dim3((unsigned)rows), dim3(256), 0, s, x, cols, out);
+    hipLaunchKernelGGL((row_norm2_kernel<true>), dim3((unsigned)rows), dim3(256), 0, s, x, cols, out, vec);
   else
-    hipLaunchKernelGGL((row_norm2_kernel<false>), dim3((unsigned)rows), dim3(256), 0, s, x, cols, out);
+    hipLaunchKernelGGL((row_norm2_kernel<false>), dim3((unsigned)rows), dim3(256), 0, s, x, cols, out, vec);
   return hipGetLastError();
 }
 
