@@ -7,62 +7,70 @@
 
 namespace spfel {
 
-// Y[a][k][b] = sum_l X[a][l][b] W[l][k]; one thread per output element with
-// b fastest, so reads of X are contiguous in b (or broadcast when B = 1) and
-// reads of W are contiguous in k (or broadcast).
-template <bool XC, int OUT>
+// Y[a][k][b] = sum_l X[a][l][b] W[l][k]; one thread per KB consecutive
+// outputs along k (same a and b), b fastest across threads, so reads of X
+// are contiguous in b (or broadcast when B = 1), each X value serves KB
+// outputs, and reads of W are contiguous in k (or broadcast).  Every output
+// is summed over l in order, whatever KB.
+template <bool XC, int OUT, int KB>
 __global__ __launch_bounds__(256) void contract_kernel(const void *__restrict__ X_,
                                                        const float2 *__restrict__ W,
                                                        void *__restrict__ Y_, int A, int L,
                                                        int K, int B) {
-  const int64_t total = (int64_t)A * K * B;
+  const int KG = K / KB;   // K % KB == 0
+  const int64_t total = (int64_t)A * KG * B;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int b = (int)(t % B);
   const int64_t r = t / B;
-  const int k = (int)(r % K);
-  const int a = (int)(r / K);
-  float re = 0.f, im = 0.f;
+  const int k0 = (int)(r % KG) * KB;
+  const int a = (int)(r / KG);
+  float re[KB], im[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q) re[q] = im[q] = 0.f;
   const int64_t xbase = (int64_t)a * L * B + b;
-  if (XC) {
-    const float2 *X = static_cast<const float2 *>(X_);
-    for (int l = 0; l < L; ++l) {
-      const float2 x = X[xbase + (int64_t)l * B];
-      const float2 w = W[(int64_t)l * K + k];
-      re = fmaf(x.x, w.x, re);
-      re = fmaf(-x.y, w.y, re);
-      im = fmaf(x.x, w.y, im);
-      im = fmaf(x.y, w.x, im);
+  for (int l = 0; l < L; ++l) {
+    float xr, xi = 0.f;
+    if (XC) {
+      const float2 x = static_cast<const float2 *>(X_)[xbase + (int64_t)l * B];
+      xr = x.x;
+      xi = x.y;
+    } else {
+      xr = static_cast<const float *>(X_)[xbase + (int64_t)l * B];
     }
-  } else {
-    const float *X = static_cast<const float *>(X_);
-    for (int l = 0; l < L; ++l) {
-      const float x = X[xbase + (int64_t)l * B];
-      const float2 w = W[(int64_t)l * K + k];
-      re = fmaf(x, w.x, re);
-      im = fmaf(x, w.y, im);
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const float2 w = W[(int64_t)l * K + k0 + q];
+      re[q] = fmaf(xr, w.x, re[q]);
+      if (XC) re[q] = fmaf(-xi, w.y, re[q]);
+      im[q] = fmaf(xr, w.y, im[q]);
+      if (XC) im[q] = fmaf(xi, w.x, im[q]);
     }
   }
-  if (OUT == 0) {
-    static_cast<float2 *>(Y_)[t] = make_float2(re, im);
-  } else if (OUT == 1) {
-    static_cast<float *>(Y_)[t] = re;
-  } else if (OUT == 2) {
-    static_cast<float *>(Y_)[t] += re;
-  } else {
-    float2 *Y = static_cast<float2 *>(Y_);
-    const float2 y = Y[t];
-    Y[t] = make_float2(y.x + re, y.y + im);
+#pragma unroll
+  for (int q = 0; q < KB; ++q) {
+    const int64_t o = ((int64_t)a * K + k0 + q) * B + b;
+    if (OUT == 0) {
+      static_cast<float2 *>(Y_)[o] = make_float2(re[q], im[q]);
+    } else if (OUT == 1) {
+      static_cast<float *>(Y_)[o] = re[q];
+    } else if (OUT == 2) {
+      static_cast<float *>(Y_)[o] += re[q];
+    } else {
+      float2 *Y = static_cast<float2 *>(Y_);
+      const float2 y = Y[o];
+      Y[o] = make_float2(y.x + re[q], y.y + im[q]);
+    }
   }
 }
 
-hipError_t launch_contract(const void *X, bool x_complex, const float2 *W, void *Y,
-                           int out_mode, int A, int L, int K, int B, hipStream_t s) {
-  const int64_t total = (int64_t)A * K * B;
-  if (total == 0) return hipSuccess;
+template <int KB>
+static hipError_t contract_kb(const void *X, bool x_complex, const float2 *W, void *Y,
+                              int out_mode, int A, int L, int K, int B, hipStream_t s) {
+  const int64_t total = (int64_t)A * (K / KB) * B;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
 #define SPFEL_CONTRACT(XC, O) \
-  hipLaunchKernelGGL((contract_kernel<XC, O>), grid, block, 0, s, X, W, Y, A, L, K, B)
+  hipLaunchKernelGGL((contract_kernel<XC, O, KB>), grid, block, 0, s, X, W, Y, A, L, K, B)
   if (x_complex) {
     switch (out_mode) {
       case 0: SPFEL_CONTRACT(true, 0); break;
@@ -80,6 +88,13 @@ hipError_t launch_contract(const void *X, bool x_complex, const float2 *W, void 
   }
 #undef SPFEL_CONTRACT
   return hipGetLastError();
+}
+
+hipError_t launch_contract(const void *X, bool x_complex, const float2 *W, void *Y,
+                           int out_mode, int A, int L, int K, int B, hipStream_t s) {
+  if ((int64_t)A * K * B == 0) return hipSuccess;
+  return K % 2 == 0 ? contract_kb<2>(X, x_complex, W, Y, out_mode, A, L, K, B, s)
+                    : contract_kb<1>(X, x_complex, W, Y, out_mode, A, L, K, B, s);
 }
 
 // Zero fill with a kernel (kept out of memset nodes so callers may capture
