@@ -13,7 +13,7 @@ namespace spfel {
 // when B = 1), each X value serves KB outputs, and reads of W are
 // contiguous in k (or broadcast).  Every output is summed over l in order,
 // whatever KB.
-template <bool XC, int OUT, int KB>
+template <bool XC, int OUT, int KB, bool PART>
 __global__ __launch_bounds__(256) void contract_kernel(const void *__restrict__ X_,
                                                        const float2 *__restrict__ W,
                                                        void *__restrict__ Y_, int A, int L,
@@ -41,8 +41,9 @@ __global__ __launch_bounds__(256) void contract_kernel(const void *__restrict__ 
     }
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
-      // past the end of k (odd K), read the last column; the sum is dropped
-      const float2 w = W[(int64_t)l * K + min(k0 + q, K - 1)];
+      // PART (K % KB != 0): past the end of k, read the last column; the sum
+      // is dropped
+      const float2 w = W[(int64_t)l * K + (PART ? min(k0 + q, K - 1) : k0 + q)];
       re[q] = fmaf(xr, w.x, re[q]);
       if (XC) re[q] = fmaf(-xi, w.y, re[q]);
       im[q] = fmaf(xr, w.y, im[q]);
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void contract_kernel(const void *__restrict__ 
   }
 #pragma unroll
   for (int q = 0; q < KB; ++q) {
-    if (k0 + q >= K) break;
+    if (PART && k0 + q >= K) break;
     const int64_t o = ((int64_t)a * K + k0 + q) * B + b;
     if (OUT == 0) {
       static_cast<float2 *>(Y_)[o] = make_float2(re[q], im[q]);
@@ -67,13 +68,13 @@ __global__ __launch_bounds__(256) void contract_kernel(const void *__restrict__ 
   }
 }
 
-template <int KB>
+template <int KB, bool PART>
 static hipError_t contract_kb(const void *X, bool x_complex, const float2 *W, void *Y,
                               int out_mode, int A, int L, int K, int B, hipStream_t s) {
   const int64_t total = (int64_t)A * ((K + KB - 1) / KB) * B;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
 #define SPFEL_CONTRACT(XC, O) \
-  hipLaunchKernelGGL((contract_kernel<XC, O, KB>), grid, block, 0, s, X, W, Y, A, L, K, B)
+  hipLaunchKernelGGL((contract_kernel<XC, O, KB, PART>), grid, block, 0, s, X, W, Y, A, L, K, B)
   if (x_complex) {
     switch (out_mode) {
       case 0: SPFEL_CONTRACT(true, 0); break;
@@ -96,7 +97,8 @@ static hipError_t contract_kb(const void *X, bool x_complex, const float2 *W, vo
 hipError_t launch_contract(const void *X, bool x_complex, const float2 *W, void *Y,
                            int out_mode, int A, int L, int K, int B, hipStream_t s) {
   if ((int64_t)A * K * B == 0) return hipSuccess;
-  return contract_kb<2>(X, x_complex, W, Y, out_mode, A, L, K, B, s);
+  return K % 2 == 0 ? contract_kb<2, false>(X, x_complex, W, Y, out_mode, A, L, K, B, s)
+                    : contract_kb<2, true>(X, x_complex, W, Y, out_mode, A, L, K, B, s);
 }
 
 // Zero fill with a kernel (kept out of memset nodes so callers may capture
