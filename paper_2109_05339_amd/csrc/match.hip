@@ -24,8 +24,9 @@ constexpr int kGroup = 8;  // m-tiles per launch-order group
 
 // Tile of a block: blocks are dealt round-robin to the 8 XCDs, so the block
 // id is first remapped to make each XCD's blocks a contiguous range, and
-// that range is walked m-fastest in groups of kGroup m-tiles, so the blocks
+// that range is walked m-fastest in groups of `group` m-tiles, so the blocks
 // resident on one XCD share slabs of S and D in that XCD's L2.
+template <int group = kGroup>
 __device__ inline void tile_of_block(int tiles_m, int tiles_n, int splits, int &tm, int &tn,
                                      int &split) {
   const int G = gridDim.x, bid = blockIdx.x;
@@ -34,10 +35,10 @@ __device__ inline void tile_of_block(int tiles_m, int tiles_n, int splits, int &
   const int tiles = tiles_m * tiles_n;
   split = v / tiles;
   v -= split * tiles;
-  const int gsize = kGroup * tiles_n;
+  const int gsize = group * tiles_n;
   const int g = v / gsize;
-  const int first = g * kGroup;
-  const int gm = min(tiles_m - first, kGroup);
+  const int first = g * group;
+  const int gm = min(tiles_m - first, group);
   const int w = v - g * gsize;
   tm = first + w % gm;
   tn = w / gm;
