@@ -103,3 +103,65 @@ def topk_certified(b, ebf, k: int = 8) -> np.ndarray:
     bk1 = b[order[k], cols]
     e1 = ebf[order[0], cols]
     return (bk1 - b1) > (e1 + ebf.max(axis=0))
+
+
+# ---------------------------------------------------------------------------
+# Centred BF16 proxy (the precision form of section II-B: BF16 products with
+# FP32 accumulation nominate candidates, an FP32 rescore decides).
+#
+# Reading: subtracting one vector c from every model image and every image
+# leaves each distance unchanged, |(s - c) - (d - c)| = |s - d|, and removes
+# the bright low-q intensity all slices and images share, so BF16 rounding
+# acts on the small centred values.  With s^ = bf16(s - c) and d^ = bf16(d
+# - c), the proxy b = |s^ - d^|^2 is a true squared distance, and the
+# triangle inequality gives |sqrt(D) - sqrt(b)| <= e_m + f_n with the
+# per-row rounding-error norms e_m = |s^ - (s - c)|, f_n = |d^ - (d - c)|.
+
+
+def centre_rounded_mean(D) -> np.ndarray:
+    """Per-pixel centre: the mean of the images' values at each pixel,
+    rounded to the nearest integer (ties to even), so centred photon counts
+    stay integers.  Returned as float32."""
+    D = np.asarray(D, dtype=np.float64)
+    return np.round(D.mean(axis=0)).astype(np.float32)
+
+
+def bf16_centred(X, c):
+    """(values, squared norms, rounding-error norms) of bf16(x - c) per row.
+
+    x - c is formed in float32 (one IEEE subtraction per element), then
+    rounded to BF16 (nearest, ties to even).  norm2 = sum_p v_p^2 of the BF16
+    values v; err = |v - (x - c)| with x - c exact (float64)."""
+    X32 = np.asarray(X, dtype=np.float32)
+    c32 = np.asarray(c, dtype=np.float32)
+    xc = X32 - c32[None, :]                      # float32 subtraction
+    v = bf16_round(xc).astype(np.float64)
+    exact = X32.astype(np.float64) - c32.astype(np.float64)[None, :]
+    norm2 = (v * v).sum(axis=1)
+    err = np.sqrt(((v - exact) ** 2).sum(axis=1))
+    return v, norm2, err
+
+
+def centred_proxy(Sv, Dv) -> np.ndarray:
+    """Exact squared distances between the BF16 rows: b[m, n] = |s^_m - d^_n|^2."""
+    return distances_expanded(Sv, Dv)
+
+
+def centred_certificate(b, e, f, D_exact, k: int = 8) -> np.ndarray:
+    """Per image n, whether the k smallest proxies contain every minimiser of
+    the exact distance: each row m outside the k has sqrt(D_mn) >=
+    sqrt(b_mn) - e_m - f_n, so the top-k is certified when that lower bound
+    exceeds sqrt(min over the top-k of D) for every m outside it."""
+    b = np.asarray(b)
+    top = topk(b, k)
+    out = np.empty(b.shape[1], dtype=bool)
+    M = b.shape[0]
+    for n in range(b.shape[1]):
+        inside = np.zeros(M, dtype=bool)
+        inside[top[:, n]] = True
+        if inside.all():
+            out[n] = True
+            continue
+        lb = np.sqrt(np.maximum(b[~inside, n], 0.0)) - np.asarray(e)[~inside] - f[n]
+        out[n] = lb.min() > np.sqrt(np.asarray(D_exact)[top[:, n], n].min())
+    return out
