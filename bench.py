@@ -1,19 +1,24 @@
 """Slice-and-match throughput on one MI355X.
 
-Workload (default): 65^3 float32 intensity model of a 200-scatterer
-molecule, 128 x 128 detector (16,384 Ewald-sphere pixels), 10,000 reference
-orientations, 2,048 Poisson images at 20 photons/pixel.  One step is one
-pass of the orientation-determination hot path over that batch:
+Default workload (the largest one-GPU configuration): 129^3 float32
+intensity model of a 500-scatterer molecule, 256 x 256 detector (65,536
+Ewald-sphere pixels), 100,000 reference orientations streamed in chunks of
+8,192, 16,384 Poisson images at 5 photons/pixel.  One step is one pass of
+the whole hot path over that batch:
 
-  set_model (deconvolve + separable transform to the 130^3 fine grid)
-  -> slice all 10,000 orientations (type-2 NUFFT, float32, + norms)
-  -> match every image against every slice (float32 MFMA GEMM + argmin).
+  set_model (deconvolve + separable transform to the 258^3 fine grid)
+  -> for each chunk of 8,192 orientations: type-2 slicing (float32), the
+     centred BF16 operands, the BF16 distance GEMM with per-tile top-8,
+     certified FP32 rescore into the running best
+  -> type-1 merge (adjoint spread + transform) of every image at its
+     matched orientation.
 
 The JSON line reports pixel-comparisons/s = M * n_img * P / step time
-(inputs resident in HBM), the float32 distance GEMM against the MI355X
-float32 matrix peak, the BF16+rescore matcher on the same inputs (time and
-argmin agreement with float32), the type-2 and type-1 NUFFT point rates,
-and the CPU oracle timed on a bounded sample on this host.
+(inputs resident in HBM), the per-kernel times measured with HIP events on
+the launch stream inside the timed steps, the dominant kernel against its
+roofline, BF16-vs-FP32 argmin agreement on an image subset, and the CPU
+oracle timed on a bounded sample on this host.  ``--config 2`` times the
+FP32 form (65^3, 128^2, 10^4 x 2,048); ``--config 4`` the loss + gradient.
 """
 from __future__ import annotations
 
@@ -35,7 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # 256 CUs x 64 lanes x 2 flop x 2.4 GHz: FP32 fused multiply-add without the
 # packed (two-per-lane) form, which this build does not emit
 PEAK_FP32_VECTOR_TFLOPS = 78.6
-# algorithmic work of one interpolated point at w = 6: w^3 multiply-adds
+# algorithmic work of one interpolated (or spread) point at w = 6: w^3
+# multiply-adds
 INTERP_FLOP_PER_POINT = 2 * 6 ** 3
 
 
@@ -46,14 +52,18 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload id (2: the default above)")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=5, help="workload id (5: the default above)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip BF16 and spread side runs")
-    ap.add_argument("--cpu-sample", type=int, default=200, help="orientations in the oracle sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the agreement check and the workload-2 figures")
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="orientations the oracle slices in the CPU baseline")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle process pool size (0: the CPUs this process may use, at most 16)")
     ap.add_argument("--counters", action="store_true",
-                    help="counter-collection run: one step of each path and a plain 1 GiB "
+                    help="counter-collection run: one chunk of each hot kernel and a plain 1 GiB "
                          "device copy (the copy calibrates FETCH_SIZE/WRITE_SIZE), no timing")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs of --counters (FETCH_SIZE, then "
@@ -70,6 +80,8 @@ CSRC = os.path.join(ROOT, "paper_2109_05339_amd", "csrc")
 KERNEL_SOURCES = {
     "interp_tiled_kernel": ["interp.hip", "device_common.h", "internal.h"],
     "match_f32_kernel": ["match.hip", "device_common.h", "internal.h"],
+    "match_bf16_big_kernel": ["match.hip", "device_common.h", "internal.h"],
+    "spread_mfma_kernel": ["spread.hip", "device_common.h", "internal.h"],
 }
 COPY_BYTES = 1 << 30
 
@@ -156,215 +168,65 @@ def main() -> int:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one "
               "GPU and the multi-GPU form of this path is a design, not a build", file=sys.stderr)
         return 2
-    import torch
     import synth
-    import paper_2109_05339_amd as spfel
-
     cfg = synth.config(args.config)
+    cpu = None
+    if not args.no_cpu_baseline and not args.counters and args.config in (2, 5):
+        # before the GPU is touched: the oracle's process pool forks from here
+        cpu = cpu_baseline(cfg, args)
+    import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.config == 5:
-        return bench_streaming(args, cfg, dev)
     if args.config == 4:
         return bench_gradient(args, cfg, dev)
-    M, n_img, P, N = cfg.n_refs, cfg.n_images, cfg.n_pix, cfg.n_model
-
-    # ---- inputs (not timed) ----
-    t0 = time.time()
-    m_host, _ = synth.intensity_model(cfg)
-    det = torch.from_numpy(synth.detector_q(cfg.n_det).astype(np.float32)).to(dev)
-    ref_q = torch.from_numpy(synth.quaternions(cfg, "ref_quats", M).astype(np.float32)).to(dev)
-    img_q = torch.from_numpy(synth.quaternions(cfg, "image_quats", n_img).astype(np.float32)).to(dev)
-    plan = spfel.Plan(N, device=dev)
-    plan.set_detector(det)
-    plan.set_model(torch.from_numpy(m_host.astype(np.float32)).to(dev))
-    lam0 = plan.slice(img_q)[0].clamp_(min=0).cpu().numpy()
-    alpha = synth.photon_scale(lam0, cfg.photons)
-    images = torch.from_numpy(synth.poisson_counts(cfg, alpha * lam0)).to(dev)
-    del lam0
-    model = torch.from_numpy((alpha * m_host).astype(np.float32)).to(dev)
-    dnorm = spfel.row_norm2(images)
-    images_bf16 = images.to(torch.bfloat16)
-    images_x3 = spfel.split_bf16(images)
-    ws = torch.empty((max(spfel.match_workspace_bytes(M, n_img, P, m)
-                          for m in (spfel.MATCH_FP32, spfel.MATCH_BF16_RESCORE8,
-                                    spfel.MATCH_BF16X3_RESCORE8)),),
-                     dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-    log(f"inputs ready in {time.time() - t0:.1f}s: M={M} n_img={n_img} P={P} N={N}")
-
-    stream = torch.cuda.current_stream(dev)
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-
-    def step(mode, marks=None):
-        """One pass: set_model, slice all orientations (with norms, and the
-        BF16 forms the mode needs), match every image against every slice."""
-        e = [ev() for _ in range(2)] if marks is not None else None
-        if e: e[0].record(stream)
-        plan.set_model(model)
-        S, Sb, sn = plan.slice(ref_q, out=True, bf16=mode == spfel.MATCH_BF16_RESCORE8, norms=True)
-        bi, bd = spfel.new_best(n_img, dev)
-        if mode == spfel.MATCH_FP32:
-            spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
-        elif mode == spfel.MATCH_BF16_RESCORE8:
-            spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=mode, slices_f32=S,
-                        images_f32=images, workspace=ws)
-        else:
-            spfel.match(spfel.split_bf16(S), sn, images_x3, dnorm, bi, bd, mode=mode,
-                        slices_f32=S, images_f32=images, workspace=ws)
-        if e: e[1].record(stream)
-        if marks is not None:
-            marks.append(e)
-        return bi, bd
-
-    step_fp32 = lambda marks=None: step(spfel.MATCH_FP32, marks)  # noqa: E731
-    step_bf16 = lambda marks=None: step(spfel.MATCH_BF16_RESCORE8, marks)  # noqa: E731
-    step_bf16x3 = lambda marks=None: step(spfel.MATCH_BF16X3_RESCORE8, marks)  # noqa: E731
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        marks = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn(marks)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / steps
-        step_ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
-        return wall * 1e3, step_ms
-
-    def kernel_times(reps):
-        """Unpipelined launches of the two hot kernels, each bracketed by
-        HIP events on its own (the current) stream."""
-        plan.set_model(model)
-        S, _, sn = plan.slice(ref_q, norms=True)
-        bi, bd = spfel.new_best(n_img, dev)
-        spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
-        torch.cuda.synchronize()
-        t_slice, t_match = [], []
-        for _ in range(reps):
-            a, b, c = ev(), ev(), ev()
-            a.record(stream)
-            plan.slice(ref_q, out=True, norms=False)
-            b.record(stream)
-            bi, bd = spfel.new_best(n_img, dev)
-            c.record(stream)
-            d = ev()
-            spfel.match(S, sn, images, dnorm, bi, bd, workspace=ws)
-            d.record(stream)
-            t_slice.append((a, b))
-            t_match.append((c, d))
-        torch.cuda.synchronize()
-        return (float(np.mean([a.elapsed_time(b) for a, b in t_slice])),
-                float(np.mean([c.elapsed_time(d) for c, d in t_match])))
-
-    if args.counters:
-        kernel_times(1)
-        step_bf16()
-        plan.merge_adjoint(ref_q[:n_img].contiguous(), None, images)
-        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("counter run done: unpipelined slice + fp32 match, one bf16 step, one merge, one 1 GiB copy")
-        print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 4}), flush=True)
-        return 0
-
-    log(f"timing fp32 path: {args.warmup} warmup + {args.steps} steps")
-    wall_ms, step_ms = timed(step_fp32, args.steps, args.warmup)
-    ms_per_step = max(wall_ms, step_ms)
-    comps = float(M) * n_img * P
-    value = comps / (ms_per_step * 1e-3)
-    slice_ms, match_ms = kernel_times(max(3, args.steps // 2))
-    gemm_flops = 2.0 * comps
-    gemm_tf = gemm_flops / (match_ms * 1e-3) / 1e12
-    interp_tf = INTERP_FLOP_PER_POINT * M * P / (slice_ms * 1e-3) / 1e12
-    log(f"fp32 step {ms_per_step:.3f} ms; unpipelined slice {slice_ms:.3f} ms, match {match_ms:.3f} ms")
-    roof_match = {"kernel": "match_f32_kernel", "bound": "mfma", "achieved": gemm_tf,
-                  "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                  "frac": gemm_tf / PEAK_FP32_MFMA_TFLOPS,
-                  "traffic": traffic_of("match_f32_kernel", args.config)}
-    roof_interp = {"kernel": "interp_tiled_kernel", "bound": "alu", "achieved": interp_tf,
-                   "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                   "frac": interp_tf / PEAK_FP32_VECTOR_TFLOPS,
-                   "traffic": traffic_of("interp_tiled_kernel", args.config)}
-    dominant = roof_interp if slice_ms >= match_ms else roof_match
-
-    out = {
-        "metric": "slice+match pixel-comparisons/s",
-        "value": value,
-        "unit": "pixel-comparisons/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"{N}^3 float32 intensity model ({cfg.n_atoms} scatterers), "
-                         f"{cfg.n_det}x{cfg.n_det} detector, {M} reference orientations, "
-                         f"{n_img} Poisson images at {cfg.photons:g} photons/px; step = "
-                         "set_model + type-2 slicing + float32 distance GEMM with argmin"),
-            "M": M, "n_img": n_img, "P": P, "N": N, "kernel_width": 6, "upsampfac": 2.0,
-        },
-        "unpipelined_ms": {"slice_all": slice_ms, "match_fp32_all": match_ms},
-        "nufft_type2_pts_per_s": M * P / (slice_ms * 1e-3),
-        "roofline": dominant,
-        "roofline_kernels": [roof_interp, roof_match],
-    }
-
-    if not args.no_extras:
-        bi32, _ = step_fp32()
-        for name, fn in (("bf16_rescore", step_bf16), ("bf16x3_rescore", step_bf16x3)):
-            log(f"timing {name} path")
-            wall_b, step_b = timed(fn, max(5, args.steps // 2), 2)
-            bib, _ = fn()
-            agree = float((bib == bi32).float().mean())
-            out[name] = {
-                "ms_per_step": max(wall_b, step_b),
-                "pixel_comparisons_per_s": comps / (max(wall_b, step_b) * 1e-3),
-                "argmin_agreement_vs_fp32": agree,
-            }
-            log(f"{name} step {max(wall_b, step_b):.3f} ms, agreement {agree:.4f}")
-        # BF16 GEMM kernel alone (unpipelined) on the same slices
-        plan.set_model(model)
-        S, Sb, sn = plan.slice(ref_q, bf16=True, norms=True)
-        a, b = ev(), ev()
-        torch.cuda.synchronize()
-        a.record(stream)
-        for _ in range(5):
-            bi, bd = spfel.new_best(n_img, dev)
-            spfel.match(Sb, sn, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
-                        slices_f32=S, images_f32=images, workspace=ws)
-        b.record(stream)
-        torch.cuda.synchronize()
-        t = a.elapsed_time(b) / 5
-        out["bf16_rescore"]["match_ms_unpipelined"] = t
-        del S, Sb, sn
-        # type-1 spread of every image at its matched orientation (merge A* b)
-        mq = ref_q[bi32.long()].contiguous()
-        plan.merge_adjoint(mq, None, images)
-        torch.cuda.synchronize()
-        a, b = ev(), ev()
-        reps = 5
-        a.record(stream)
-        for _ in range(reps):
-            plan.merge_adjoint(mq, None, images)
-        b.record(stream)
-        torch.cuda.synchronize()
-        t1 = a.elapsed_time(b) / reps
-        out["merge_adjoint_ms"] = t1
-        out["nufft_type1_pts_per_s"] = n_img * P / (t1 * 1e-3)
-        log(f"merge_adjoint {t1:.3f} ms")
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, m_host, n_img, args.cpu_sample, comps)
+    if args.config == 5:
+        out = bench_streaming(args, cfg, dev)
+        if out is None:
+            return 0
+        if not args.no_extras:
+            log("workload 2 figures (FP32 form)")
+            out["workload2"] = bench_plain(args, synth.config(2), dev, steps=10, warmup=2)
+    else:
+        out = bench_plain(args, cfg, dev, args.steps, args.warmup)
+        if out is None:
+            return 0
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
+
+
+class Timer:
+    """HIP events recorded on the launch stream; durations per label."""
+
+    def __init__(self, torch, stream, on=True):
+        self.torch, self.stream, self.on = torch, stream, on
+        self.marks = {}
+
+    def span(self, label):
+        timer = self
+
+        class _Span:
+            def __enter__(self):
+                if timer.on:
+                    self.a = timer.torch.cuda.Event(enable_timing=True)
+                    self.a.record(timer.stream)
+
+            def __exit__(self, *exc):
+                if timer.on:
+                    b = timer.torch.cuda.Event(enable_timing=True)
+                    b.record(timer.stream)
+                    timer.marks.setdefault(label, []).append((self.a, b))
+        return _Span()
+
+    def ms(self, label):
+        return [a.elapsed_time(b) for a, b in self.marks.get(label, [])]
+
+
+def roofline(kernel, bound, work, ms, peak, unit, traffic):
+    achieved = work / (ms * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+    return {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic, "launch_ms": ms}
 
 
 def _render_images(plan, cfg, dev, quats, m_host, chunk=2048):
@@ -387,10 +249,10 @@ def _render_images(plan, cfg, dev, quats, m_host, chunk=2048):
 
 
 def bench_streaming(args, cfg, dev):
-    """Workload 5: 100,000 reference orientations streamed in chunks of 8,192
-    (sliced and never stored in full), BF16 matcher with per-chunk top-8
-    FP32 rescoring into a running best, then the type-1 merge of all images
-    at their matched orientations."""
+    """Workload 5, the default: 100,000 reference orientations streamed in
+    chunks of 8,192 (sliced and never stored in full), centred BF16 matcher
+    with certified per-chunk FP32 rescoring into a running best, then the
+    type-1 merge of all images at their matched orientations."""
     import torch
     import synth
     import paper_2109_05339_amd as spfel
@@ -404,43 +266,75 @@ def bench_streaming(args, cfg, dev):
     plan.set_detector(det)
     images, alpha = _render_images(plan, cfg, dev, img_q, m_host)
     model = torch.from_numpy((alpha * m_host).astype(np.float32)).to(dev)
-    dnorm = spfel.row_norm2(images)
-    images_bf16 = images.to(torch.bfloat16)
+    im = spfel.ImagesBF16(images)     # centre = rounded per-pixel image mean
     merged = torch.empty((N, N, N), dtype=torch.float32, device=dev)
+    flags = torch.zeros((n_img,), dtype=torch.int32, device=dev)
+    ws = torch.empty((spfel.match_workspace_bytes(C, n_img, P, spfel.MATCH_BF16_RESCORE8),),
+                     dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     log(f"workload 5 inputs ready in {time.time() - t0:.1f}s")
     stream = torch.cuda.current_stream(dev)
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    chunks = [(c0, min(M, c0 + C)) for c0 in range(0, M, C)]
 
-    def step(marks=None):
-        e = [ev() for _ in range(3)] if marks is not None else None
-        if e: e[0].record(stream)
-        plan.set_model(model)
+    def step(tm):
+        with tm.span("set_model"):
+            plan.set_model(model)
         bi, bd = spfel.new_best(n_img, dev)
-        plan.orient(ref_q, images_bf16, dnorm, bi, bd, mode=spfel.MATCH_BF16_RESCORE8, chunk=C,
-                    images_f32=images, overlap=False)
-        if e: e[1].record(stream)
-        plan.merge_adjoint(ref_q[bi.long()].contiguous(), None, images, out=merged)
-        if e: e[2].record(stream)
-        if marks is not None:
-            marks.append(e)
-        return bi
+        flags.zero_()
+        for c0, c1 in chunks:
+            full = c1 - c0 == C
+            with tm.span("slice" if full else "slice_tail"):
+                S, _ = plan.slice(ref_q[c0:c1])
+            with tm.span("centre" if full else "centre_tail"):
+                sb, sn, se = spfel.bf16_centred(S, im.centre)
+            with tm.span("match" if full else "match_tail"):
+                spfel.match(sb, sn, im.b16, im.norm2, bi, bd, m_offset=c0,
+                            mode=spfel.MATCH_BF16_RESCORE8, slices_f32=S, images_f32=images,
+                            slice_err=se, image_err=im.err, flags=flags, workspace=ws)
+            del S, sb
+        with tm.span("merge"):
+            plan.merge_adjoint(ref_q[bi.long()].contiguous(), None, images, out=merged)
+        return bi, bd
+
+    if args.counters:
+        with torch.no_grad():
+            S, _ = plan.slice(ref_q[:C])
+            sb, sn, se = spfel.bf16_centred(S, im.centre)
+            bi, bd = spfel.new_best(n_img, dev)
+            spfel.match(sb, sn, im.b16, im.norm2, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
+                        slices_f32=S, images_f32=images, slice_err=se, image_err=im.err,
+                        workspace=ws)
+            plan.merge_adjoint(ref_q[:n_img].contiguous(), None, images, out=merged)
+            _copy_calibration(torch, dev)
+        return None
 
     for _ in range(args.warmup):
-        step()
+        step(Timer(torch, stream, on=False))
     torch.cuda.synchronize()
-    marks = []
+    tm = Timer(torch, stream)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(marks)
+        bi, bd = step(tm)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps * 1e3
-    match_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in marks]))
-    merge_ms = float(np.mean([b.elapsed_time(c) for _, b, c in marks]))
     comps = float(M) * n_img * P
+    per = {k: float(np.mean(tm.ms(k))) for k in tm.marks}
+    tot = {k: float(np.sum(tm.ms(k))) / args.steps for k in tm.marks}
+    full = len([c for c in chunks if c[1] - c[0] == C])
+    r_slice = roofline("interp_tiled_kernel", "alu", INTERP_FLOP_PER_POINT * C * P, per["slice"],
+                       PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s", traffic_of("interp_tiled_kernel", 5))
+    r_match = roofline("match_bf16_big_kernel + rescore", "mfma", 2.0 * C * n_img * P,
+                       per["match"], PEAK_BF16_MFMA_TFLOPS, "TFLOP/s",
+                       traffic_of("match_bf16_big_kernel", 5))
+    r_merge = roofline("spread_mfma_kernel + transform", "alu", INTERP_FLOP_PER_POINT * n_img * P,
+                       per["merge"], PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s",
+                       traffic_of("spread_mfma_kernel", 5))
+    share = {"slice": tot["slice"], "match": tot["match"], "merge": tot["merge"]}
+    dominant = {"slice": r_slice, "match": r_match, "merge": r_merge}[max(share, key=share.get)]
+    fl = flags.cpu().numpy()
     out = {
         "metric": "slice+match pixel-comparisons/s",
-        "value": comps / (match_ms * 1e-3),
+        "value": comps / (wall * 1e-3),
         "unit": "pixel-comparisons/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -448,14 +342,168 @@ def bench_streaming(args, cfg, dev):
         "config": {"workload": (f"{N}^3 float32 model ({cfg.n_atoms} scatterers), {cfg.n_det}x"
                                 f"{cfg.n_det} detector, {M} reference orientations streamed in "
                                 f"chunks of {C}, {n_img} Poisson images at {cfg.photons:g} "
-                                "photons/px; BF16 matcher with per-chunk top-8 FP32 rescore, "
-                                "then the type-1 merge of all images at their matched orientations"),
+                                "photons/px; step = set_model + per chunk (type-2 slicing, "
+                                "centred BF16 operands, BF16 distance GEMM with top-8, certified "
+                                "FP32 rescore) + type-1 merge of all images at their matched "
+                                "orientations"),
                    "M": M, "n_img": n_img, "P": P, "N": N, "chunk": C},
-        "breakdown_ms": {"stream_slice+match": match_ms, "merge_adjoint": merge_ms},
+        "breakdown_ms_per_step": {k: tot[k] for k in sorted(tot)},
+        "per_full_chunk_ms": {"slice": per["slice"], "centre": per["centre"], "match": per["match"],
+                              "full_chunks": full},
+        "nufft_type2_pts_per_s": C * P / (per["slice"] * 1e-3),
+        "nufft_type1_pts_per_s": n_img * P / (per["merge"] * 1e-3),
+        "certified_fraction": float(np.mean(fl == 0)),
+        "roofline": dominant,
+        "roofline_kernels": [r_slice, r_match, r_merge],
+    }
+    log(f"step {wall:.1f} ms; per full chunk slice {per['slice']:.2f} ms, centre "
+        f"{per['centre']:.2f} ms, match {per['match']:.2f} ms; merge {per['merge']:.1f} ms; "
+        f"certified {out['certified_fraction']:.4f}")
+    if not args.no_extras:
+        out["bf16_vs_fp32"] = agreement_subset(plan, model, ref_q, images, bi, chunks, dev)
+    return out
+
+
+def agreement_subset(plan, model, ref_q, images, bi_bf16, chunks, dev, n_sub=1024):
+    """The FP32 matcher (expanded form, float32 MFMA GEMM) over every
+    reference orientation for the first n_sub images; fraction of images on
+    which its argmin equals the BF16 path's."""
+    import torch
+    import paper_2109_05339_amd as spfel
+    sub = images[:n_sub].contiguous()
+    dn = spfel.row_norm2(sub)
+    bi, bd = spfel.new_best(n_sub, dev)
+    plan.set_model(model)
+    for c0, c1 in chunks:
+        S, sn = plan.slice(ref_q[c0:c1], norms=True)
+        spfel.match(S, sn, sub, dn, bi, bd, m_offset=c0)
+        del S
+    a = bi.cpu().numpy()
+    b = bi_bf16[:n_sub].cpu().numpy()
+    log(f"bf16 vs fp32 argmin agreement on {n_sub} images: {np.mean(a == b):.4f}")
+    return {"images": n_sub, "argmin_agreement": float(np.mean(a == b))}
+
+
+def _copy_calibration(torch, dev):
+    src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("counter run done: one chunk of each hot kernel, one merge, one 1 GiB copy")
+    print(json.dumps({"counters_run": True, "copy_bytes": src.numel() * 4}), flush=True)
+
+
+def bench_plain(args, cfg, dev, steps, warmup):
+    """Workloads 1-3 (2 by default): the FP32 form.  One step = set_model +
+    slicing of all orientations with norms + FP32 distance GEMM with argmin;
+    the BF16 form's step on the same inputs is timed beside it."""
+    import torch
+    import synth
+    import paper_2109_05339_amd as spfel
+    M, n_img, P, N = cfg.n_refs, cfg.n_images, cfg.n_pix, cfg.n_model
+    t0 = time.time()
+    m_host, _ = synth.intensity_model(cfg)
+    det = torch.from_numpy(synth.detector_q(cfg.n_det).astype(np.float32)).to(dev)
+    ref_q = torch.from_numpy(synth.quaternions(cfg, "ref_quats", M).astype(np.float32)).to(dev)
+    img_q = torch.from_numpy(synth.quaternions(cfg, "image_quats", n_img).astype(np.float32)).to(dev)
+    plan = spfel.Plan(N, device=dev)
+    plan.set_detector(det)
+    images, alpha = _render_images(plan, cfg, dev, img_q, m_host)
+    model = torch.from_numpy((alpha * m_host).astype(np.float32)).to(dev)
+    f32 = spfel.ImagesF32(images)
+    b16 = spfel.ImagesBF16(images)
+    ws = torch.empty((max(spfel.match_workspace_bytes(M, n_img, P, m)
+                          for m in (spfel.MATCH_FP32, spfel.MATCH_BF16_RESCORE8)),),
+                     dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"workload {cfg.cid} inputs ready in {time.time() - t0:.1f}s: M={M} n_img={n_img} P={P}")
+    stream = torch.cuda.current_stream(dev)
+
+    def step_fp32(tm):
+        with tm.span("set_model"):
+            plan.set_model(model)
+        with tm.span("slice"):
+            S, sn = plan.slice(ref_q, norms=True)
+        bi, bd = spfel.new_best(n_img, dev)
+        with tm.span("match"):
+            spfel.match(S, sn, f32.x, f32.norm2, bi, bd, workspace=ws)
+        return bi
+
+    def step_bf16(tm):
+        with tm.span("set_model"):
+            plan.set_model(model)
+        with tm.span("slice"):
+            S, _ = plan.slice(ref_q)
+        with tm.span("centre"):
+            sb, sn, se = spfel.bf16_centred(S, b16.centre)
+        bi, bd = spfel.new_best(n_img, dev)
+        with tm.span("match"):
+            spfel.match(sb, sn, b16.b16, b16.norm2, bi, bd, mode=spfel.MATCH_BF16_RESCORE8,
+                        slices_f32=S, images_f32=images, slice_err=se, image_err=b16.err,
+                        workspace=ws)
+        return bi
+
+    if args.counters:
+        step_fp32(Timer(torch, stream, on=False))
+        step_bf16(Timer(torch, stream, on=False))
+        plan.merge_adjoint(ref_q[:n_img].contiguous(), None, images)
+        _copy_calibration(torch, dev)
+        return None
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn(Timer(torch, stream, on=False))
+        torch.cuda.synchronize()
+        tm = Timer(torch, stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bi = fn(tm)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3, tm, bi
+
+    wall, tm, bi32 = timed(step_fp32)
+    comps = float(M) * n_img * P
+    per = {k: float(np.mean(tm.ms(k))) for k in tm.marks}
+    r_slice = roofline("interp_tiled_kernel", "alu", INTERP_FLOP_PER_POINT * M * P, per["slice"],
+                       PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s",
+                       traffic_of("interp_tiled_kernel", cfg.cid))
+    r_match = roofline("match_f32_kernel", "mfma", 2.0 * comps, per["match"],
+                       PEAK_FP32_MFMA_TFLOPS, "TFLOP/s", traffic_of("match_f32_kernel", cfg.cid))
+    log(f"fp32 step {wall:.3f} ms; slice {per['slice']:.3f} ms, match {per['match']:.3f} ms")
+    wall_b, tmb, bib = timed(step_bf16)
+    perb = {k: float(np.mean(tmb.ms(k))) for k in tmb.marks}
+    agree = float((bib == bi32).float().mean())
+    log(f"bf16 step {wall_b:.3f} ms, agreement {agree:.4f}")
+    # type-1 merge of every image at its matched orientation
+    mq = ref_q[bi32.long()].contiguous()
+    tmm = Timer(torch, stream)
+    for _ in range(3):
+        with tmm.span("merge"):
+            plan.merge_adjoint(mq, None, images)
+    torch.cuda.synchronize()
+    merge_ms = float(np.mean(tmm.ms("merge")[1:]))
+    return {
+        "metric": "slice+match pixel-comparisons/s",
+        "value": comps / (wall * 1e-3),
+        "unit": "pixel-comparisons/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{N}^3 float32 intensity model ({cfg.n_atoms} scatterers), "
+                                f"{cfg.n_det}x{cfg.n_det} detector, {M} reference orientations, "
+                                f"{n_img} Poisson images at {cfg.photons:g} photons/px; step = "
+                                "set_model + type-2 slicing + float32 distance GEMM with argmin"),
+                   "M": M, "n_img": n_img, "P": P, "N": N},
+        "kernel_ms": per,
+        "nufft_type2_pts_per_s": M * P / (per["slice"] * 1e-3),
+        "roofline": r_slice if per["slice"] >= per["match"] else r_match,
+        "roofline_kernels": [r_slice, r_match],
+        "bf16_rescore": {"ms_per_step": wall_b, "kernel_ms": perb,
+                         "pixel_comparisons_per_s": comps / (wall_b * 1e-3),
+                         "argmin_agreement_vs_fp32": agree},
+        "merge_adjoint_ms": merge_ms,
         "nufft_type1_pts_per_s": n_img * P / (merge_ms * 1e-3),
     }
-    print(json.dumps(out), flush=True)
-    return 0
 
 
 def bench_gradient(args, cfg, dev):
@@ -510,46 +558,86 @@ def bench_gradient(args, cfg, dev):
     return 0
 
 
-def cpu_baseline(cfg, model, n_img, n_sample, comps_total):
-    """The FP64 oracle on a bounded sample of the same step: the fine grid
-    once, ``n_sample`` orientations sliced, and those slices matched against
-    ``n_img`` images; scaled to the full step's pixel-comparisons/s.  Its
-    inputs come from synth alone (the workload's model and seeded Poisson
-    images of the same shape and photon level; the values do not change the
-    oracle's running time)."""
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands, in a process pool on this host.
+
+_ORACLE = {}
+
+
+def _oracle_slice(task):
+    from oracle import geometry, nufft
+    q, det = task
+    x = geometry.slice_points(q, det).reshape(-1, 3)
+    return nufft.nufft2(_ORACLE["model"], x, real=True).reshape(len(q), -1)
+
+
+def _oracle_merge(task):
+    from oracle import geometry, nufft
+    q, det, y = task
+    x = geometry.slice_points(q, det).reshape(-1, 3)
+    return nufft.nufft1(y.reshape(-1), x, _ORACLE["model"].shape[0], real=True)
+
+
+def cpu_baseline(cfg, args):
+    """The FP64 oracle on a bounded sample of the step, run before the GPU
+    is initialised: type-2 slicing of the first ``--cpu-sample`` orientations
+    of the first chunk (split over a process pool), their distances to the
+    first 1,024 images (float64 BLAS) with argmin, and the type-1 merge of
+    one image per worker.  Inputs come from synth alone (the workload's model
+    and seeded Poisson images of the same shape and photon level).  Rates are
+    measured on the sample; the step time is extrapolated linearly."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     import synth
-    from oracle import geometry, match, nufft
-    images = synth.poisson_counts(cfg, np.full((n_img, cfg.n_pix), float(cfg.photons)))
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
+    from oracle import match
+    workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+    m_host, _ = synth.intensity_model(cfg)
+    _ORACLE["model"] = m_host
     det = synth.detector_q(cfg.n_det).astype(np.float32).astype(np.float64)
-    q = synth.quaternions(cfg, "ref_quats", n_sample).astype(np.float32).astype(np.float64)
-    log(f"cpu baseline: oracle on {n_sample} orientations x {images.shape[0]} images")
-    t0 = time.perf_counter()
-    nufft.fine_grid(model, real=True)
-    t_grid = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    S = nufft.nufft2(model, geometry.slice_points(q, det).reshape(-1, 3), real=True).reshape(n_sample, -1)
-    t_slice = time.perf_counter() - t0
+    n_s = max(workers, args.cpu_sample)
+    q = synth.quaternions(cfg, "ref_quats", n_s).astype(np.float32).astype(np.float64)
+    n_match = min(1024, cfg.n_images)
+    images = synth.poisson_counts(cfg, np.full((n_match, cfg.n_pix), float(cfg.photons)))
+    log(f"cpu baseline: oracle slicing {n_s} orientations on {workers} processes")
+    ctx = mp.get_context("fork")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        parts = np.array_split(np.arange(n_s), workers)
+        t0 = time.perf_counter()
+        S = np.concatenate(list(ex.map(_oracle_slice, [(q[p], det) for p in parts])))
+        t_slice = time.perf_counter() - t0
+        log(f"cpu baseline: merging {workers} images on {workers} processes")
+        qi = synth.quaternions(cfg, "image_quats", workers).astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        f = sum(ex.map(_oracle_merge, [(qi[i:i + 1], det, images[i]) for i in range(workers)]))
+        t_merge = time.perf_counter() - t0
+    del f
     t0 = time.perf_counter()
     Dm = match.distances_expanded(S, images.astype(np.float64))
     match.argmin_first(Dm)
     t_match = time.perf_counter() - t0
-    per_orient = (t_slice + t_match) / n_sample
-    t_step = t_grid + per_orient * cfg.n_refs
+    pts_s = n_s * cfg.n_pix / t_slice
+    comps_s = n_s * n_match * cfg.n_pix / t_match
+    merge_pts_s = workers * cfg.n_pix / t_merge
+    M, n_img, P = cfg.n_refs, cfg.n_images, cfg.n_pix
+    t_step = M * P / pts_s + float(M) * n_img * P / comps_s + n_img * P / merge_pts_s
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = workers
     return {
-        "value": comps_total / t_step,
+        "value": float(M) * n_img * P / t_step,
         "unit": "pixel-comparisons/s",
-        "cores": threads,
+        "cores": workers,
         "kind": "oracle",
-        "sample": (f"{n_sample} of {cfg.n_refs} orientations sliced by the float64 oracle "
-                   f"(single-threaded NumPy) and matched against all {images.shape[0]} images "
-                   f"(float64 BLAS, {threads} threads); fine grid once; step time "
-                   f"extrapolated linearly in orientations"),
-        "sample_seconds": t_grid + t_slice + t_match,
+        "sample": (f"float64 oracle: type-2 slicing of {n_s} of the first chunk's orientations "
+                   f"({n_s * P:.3g} points) on a pool of {workers} processes; their distances "
+                   f"to the first {n_match} images with argmin (float64 BLAS, {blas} threads); "
+                   f"type-1 merge of {workers} images, one per process.  Measured rates below; "
+                   "the full step time is extrapolated linearly from them"),
+        "measured": {"type2_pts_per_s": pts_s, "match_pixel_comparisons_per_s": comps_s,
+                     "type1_pts_per_s": merge_pts_s,
+                     "seconds": {"slice": t_slice, "match": t_match, "merge": t_merge}},
         "extrapolated_step_s": t_step,
         "cpu_model": _cpu_model(),
     }

@@ -62,7 +62,7 @@ typedef enum {
 
 enum { SPFEL_REAL = 0, SPFEL_COMPLEX = 1 };
 enum { SPFEL_F32 = 0, SPFEL_BF16 = 1 };
-enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1, SPFEL_MATCH_BF16X3_RESCORE8 = 2 };
+enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1 };
 enum { SPFEL_MERGE_ACCUMULATE = 1, SPFEL_MERGE_DEFER = 2 };
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -113,14 +113,14 @@ int spfel_set_model(spfel_plan plan, const void *model, void *stream);
 
 /* Section II-A: slice the model at M orientations.  quats: M x 4 float32;
  * det_q: P x 3 float32, or NULL for the registered detector (P must then
- * equal the registered size).  Outputs (each may be NULL, not all):
+ * equal the registered size).  Outputs (either may be NULL, not both):
  *   out       M x P row-major, float32 (REAL) or complex64 (COMPLEX);
- *   out_bf16  M x P bfloat16 (round to nearest even) copy, REAL only;
- *   out_norm2 M float32 squared norms |s_m|^2 (sum of |s|^2 over P).
+ *   out_norm2 M float32 squared norms |s_m|^2 (sum of |s|^2 over P; needs
+ *             out).
  * Requires spfel_set_model.  M = 0 or P = 0 is valid (norms become 0). */
 int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
-                const float *det_q, int64_t P, void *out, uint16_t *out_bf16,
-                float *out_norm2, void *stream);
+                const float *det_q, int64_t P, void *out, float *out_norm2,
+                void *stream);
 
 /* Squared row norms of a rows x cols matrix, float32 (dtype SPFEL_F32) or
  * bfloat16 values (SPFEL_BF16), accumulated in float32 in a fixed order
@@ -128,37 +128,65 @@ int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
 int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
                     float *out, void *stream);
 
+/* Per-pixel centre for the BF16 matcher: out[p] = the mean over the rows
+ * of x[r][p] (x: rows x cols float32; float32 sums in a fixed order), rounded
+ * to the nearest integer (ties to even) when round_to_integer is nonzero,
+ * so that centred photon counts stay integers.  rows >= 1. */
+int spfel_column_mean(const float *x, int64_t rows, int64_t cols,
+                      int round_to_integer, float *out, void *stream);
+
+/* Operands of the BF16 matcher (section II-B, precision form).  For each
+ * row r of x (rows x cols float32) and the per-pixel centre c (cols float32,
+ * or NULL for zero):
+ *   out[r][p] = bf16(x[r][p] - c[p])  (float32 subtraction, then round to
+ *               nearest even);
+ *   norm2[r]  = sum_p out[r][p]^2, float32 in a fixed order (may be NULL);
+ *   err[r]    >= |out_r - (x_r - c)| with x - c exact: an upper bound on
+ *               the row's rounding-error norm (may be NULL).
+ * Subtracting one centre from model images and images leaves every distance
+ * unchanged; it removes the intensity they share, so the BF16 values carry
+ * the part that tells orientations apart. */
+int spfel_bf16_centred(const float *x, int64_t rows, int64_t cols,
+                       const float *centre, uint16_t *out, float *norm2,
+                       float *err, void *stream);
+
 /* Bytes of device workspace spfel_match needs for these sizes and mode. */
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P,
                                    int mode);
 
-/* Section II-B: for each image n, the model image m minimising
- *   D[m, n] = |s_m|^2 + |d_n|^2 - 2 s_m . d_n
- * (float32 arithmetic, lowest m on ties), merged into the caller's running
- * best: best_idx/best_dist (n_img each) are read and updated, so chunks of
- * model images can be streamed with m_offset = index of the chunk's first
- * model image.  Initialise best_idx = -1 and best_dist = +inf.
- *   mode SPFEL_MATCH_FP32: slices/images float32 M x P / n_img x P.  Each
- *     distance is a chain of at most 36 + ceil(P/32) float32 roundings.
- *   mode SPFEL_MATCH_BF16_RESCORE8: slices/images bfloat16; the products
- *     run in bfloat16 with float32 accumulation, each image keeps the 8
- *     smallest proxy distances, and those 8 are rescored exactly as above
- *     from slices_f32/images_f32 (required, float32).  The rescored
- *     distance is a chain of at most 10 + ceil(P/64) roundings.
- *   mode SPFEL_MATCH_BF16X3_RESCORE8: as above, but slices and images are
- *     2 x M x P and 2 x n_img x P bfloat16 (the hi and lo planes of
- *     spfel_split_bf16) and the proxy products are hi.hi + lo.hi + hi.lo,
- *     three BF16 matrix products per step; the proxy then carries about
- *     16 significant bits, so the 8 candidates almost always contain the
- *     float32 minimiser.
- * slice_norm2/image_norm2: float32 squared norms (spfel_row_norm2 of the
- * float32 data).  workspace: at least spfel_match_workspace_bytes bytes. */
+/* Section II-B: for each image n, the model image m minimising the
+ * Euclidean distance D[m, n] = |s_m - d_n|^2 (lowest m on ties), merged into
+ * the caller's running best: best_idx/best_dist (n_img each) are read and
+ * updated, so chunks of model images can be streamed with m_offset = index
+ * of the chunk's first model image.  Initialise best_idx = -1 and
+ * best_dist = +inf.
+ *   mode SPFEL_MATCH_FP32: slices/images float32 M x P / n_img x P;
+ *     slice_norm2/image_norm2 their float32 squared norms
+ *     (spfel_row_norm2); D = |s|^2 + |d|^2 - 2 s.d in float32, each a chain
+ *     of at most 36 + ceil(P/32) roundings.  slices_f32, images_f32,
+ *     slice_err, image_err and flags are ignored.
+ *   mode SPFEL_MATCH_BF16_RESCORE8: slices/images are the bfloat16 centred
+ *     rows of spfel_bf16_centred (one centre for both), slice_norm2/
+ *     image_norm2 and slice_err/image_err its norm2 and err outputs;
+ *     slices_f32/images_f32 the float32 rows themselves (uncentred).  The
+ *     BF16 products accumulate in float32 into the proxy b = |s^ - d^|^2 of
+ *     the rounded rows, and each image keeps the 8 smallest proxies.  Every
+ *     candidate whose bound |sqrt(D) - sqrt(b)| <= e_m + f_n (widened by the
+ *     proxy's float32 accumulation bound) leaves it able to beat the running
+ *     best is rescored in float32 as a direct sum of (s_p - d_p)^2 (a chain
+ *     of at most P/64 + 16 roundings).  The image is certified when every
+ *     model image outside the 8 is bounded away from the running best;
+ *     otherwise it is rescored against all M model images in float32 the
+ *     same way and flags[n] |= 1 (flags: n_img int32 or NULL).  best_dist
+ *     holds the float32 direct sum.
+ * workspace: at least spfel_match_workspace_bytes bytes, 256-byte aligned. */
 int spfel_match(const void *slices, const float *slice_norm2,
                 const void *images, const float *image_norm2, int64_t M,
                 int64_t n_img, int64_t P, int64_t m_offset, int mode,
                 const float *slices_f32, const float *images_f32,
-                int32_t *best_idx, float *best_dist, void *workspace,
-                size_t workspace_bytes, void *stream);
+                const float *slice_err, const float *image_err,
+                int32_t *best_idx, float *best_dist, int32_t *flags,
+                void *workspace, size_t workspace_bytes, void *stream);
 
 /* Bytes of workspace spfel_orient needs for this chunk length. */
 size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
@@ -168,28 +196,25 @@ size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
  * chunks of `chunk` and match every image against each chunk, folding into
  * the running best (best_idx/best_dist, initialised by the caller as for
  * spfel_match).  Each chunk's slices are computed on `aux_stream` into one of
- * two workspace buffers while the previous chunk is matched on `stream`, so
- * the VALU/LDS-bound interpolation and the matrix-core GEMM overlap; the
+ * two workspace buffers while the previous chunk is matched on `stream`; the
  * model slices are never stored in full.  The result equals spfel_slice of
- * each chunk followed by spfel_match with m_offset = chunk start.  REAL plans
- * only; requires spfel_set_model.  images: n_img x P float32 (FP32 mode),
- * bfloat16 (BF16 mode) or the 2 x n_img x P planes of spfel_split_bf16
- * (BF16X3 mode; images_f32 then required, as for BF16).  Work queued on
- * `stream` before the call is complete before any slice starts; every
- * result is ordered before work later queued on `stream`.  `aux_stream` may
- * equal `stream` (no overlap).  workspace: spfel_orient_workspace_bytes,
- * 256-byte aligned; calls that overlap on the same plan race. */
+ * each chunk (and, in BF16 mode, spfel_bf16_centred of it with `centre`)
+ * followed by spfel_match with m_offset = chunk start.  REAL plans only;
+ * requires spfel_set_model.  FP32 mode: images n_img x P float32 with their
+ * norms; centre, images_f32, image_err and flags ignored.  BF16 mode: images,
+ * image_norm2, image_err from spfel_bf16_centred of images_f32 with
+ * `centre`, flags as in spfel_match.  Work queued on `stream` before the
+ * call is complete before any slice starts; every result is ordered before
+ * work later queued on `stream`.  `aux_stream` may equal `stream` (no
+ * overlap).  workspace: spfel_orient_workspace_bytes, 256-byte aligned;
+ * calls that overlap on the same plan race. */
 int spfel_orient(spfel_plan plan, const float *quats, int64_t M,
                  const float *det_q, int64_t P, const void *images,
                  const float *image_norm2, const float *images_f32,
-                 int64_t n_img, int mode, int64_t chunk, int32_t *best_idx,
-                 float *best_dist, void *workspace, size_t workspace_bytes,
+                 const float *image_err, const float *centre, int64_t n_img,
+                 int mode, int64_t chunk, int32_t *best_idx, float *best_dist,
+                 int32_t *flags, void *workspace, size_t workspace_bytes,
                  void *stream, void *aux_stream);
-
-/* Split float32 values into bfloat16 planes for SPFEL_MATCH_BF16X3_RESCORE8:
- * out[0..n) = hi = bf16(x) and out[n..2n) = lo = bf16(x - hi), both round to
- * nearest even.  out holds 2 n values. */
-int spfel_split_bf16(const float *x, int64_t n, uint16_t *out, void *stream);
 
 /* Section II-C, Eq. (2) right-hand side: the type-1 NUFFT (adjoint of
  * slicing) of values at the points R(quats[n]) det_q[p] (det_q NULL: the

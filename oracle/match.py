@@ -74,35 +74,12 @@ def bf16_round(x) -> np.ndarray:
     return r.view(np.float32)
 
 
-def bf16_proxy_bound(absdot, e_fp32, exact_images: bool) -> np.ndarray:
-    """Bound on |b - D| for the BF16 proxy b = |s|^2 + |d|^2 - 2 (s~.d~)
-    with s~, d~ rounded to BF16 and FP32 norms.  Each product moves by at
-    most (2u + u^2)|s_p d_p| (u only, if every image value is exact in BF16),
-    so |b - D| <= 2 (2u + u^2) sum|s_p d_p| + e_fp32."""
-    rel = UBF if exact_images else (2.0 * UBF + UBF * UBF)
-    return 2.0 * rel * np.asarray(absdot) + np.asarray(e_fp32)
-
-
 def topk(Dmat, k: int):
     """Per column, the k smallest values' row indices, ordered by (value,
     index); shape (k, n_cols)."""
     Dm = np.asarray(Dmat)
     order = np.lexsort((np.broadcast_to(np.arange(Dm.shape[0])[:, None], Dm.shape), Dm), axis=0)
     return order[:k]
-
-
-def topk_certified(b, ebf, k: int = 8) -> np.ndarray:
-    """Per column, whether the k smallest BF16 proxies b provably contain the
-    exact argmin: b_(k+1) - b_(1) > E_(1) + max_m E_m, where E is the proxy
-    error bound (the exact minimiser m* has b_{m*} <= b_(1) + E_(1) + E_{m*})."""
-    b = np.asarray(b)
-    ebf = np.asarray(ebf)
-    order = np.argsort(b, axis=0, kind="stable")
-    cols = np.arange(b.shape[1])
-    b1 = b[order[0], cols]
-    bk1 = b[order[k], cols]
-    e1 = ebf[order[0], cols]
-    return (bk1 - b1) > (e1 + ebf.max(axis=0))
 
 
 # ---------------------------------------------------------------------------

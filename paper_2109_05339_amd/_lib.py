@@ -50,15 +50,16 @@ SIGNATURES = {
     "spfel_plan_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_sz)]),
     "spfel_set_detector": (_int, [_vp, _vp, _i64, _vp]),
     "spfel_set_model": (_int, [_vp, _vp, _vp]),
-    "spfel_slice": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "spfel_slice": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
     "spfel_row_norm2": (_int, [_vp, _int, _i64, _i64, _vp, _vp]),
+    "spfel_column_mean": (_int, [_vp, _i64, _i64, _int, _vp, _vp]),
+    "spfel_bf16_centred": (_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
     "spfel_match_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
     "spfel_match": (_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _int, _vp, _vp, _vp, _vp,
-                           _vp, _sz, _vp]),
-    "spfel_split_bf16": (_int, [_vp, _i64, _vp, _vp]),
+                           _vp, _vp, _vp, _vp, _sz, _vp]),
     "spfel_orient_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
-    "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64, _int, _i64, _vp, _vp,
-                            _vp, _sz, _vp, _vp]),
+    "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _int, _i64,
+                            _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "spfel_merge_adjoint": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _int, _vp]),
     "spfel_weighted_residual": (_int, [_vp, _vp, _vp, _vp, _i64, _flt, _vp, _vp, _vp]),
 }

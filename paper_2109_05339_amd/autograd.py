@@ -18,7 +18,7 @@ class SliceFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, model, quats, det_q, plan):
         plan.set_model(model.contiguous())
-        s, _, _ = plan.slice(quats, det_q)
+        s, _ = plan.slice(quats, det_q)
         ctx.save_for_backward(quats, det_q)
         ctx.plan = plan
         return s
@@ -42,7 +42,7 @@ class SliceLossFn(torch.autograd.Function):
         n = quats.shape[0]
         for c0 in range(0, n, chunk):
             c1 = min(n, c0 + chunk)
-            s, _, _ = plan.slice(quats[c0:c1], det_q)
+            s, _ = plan.slice(quats[c0:c1], det_q)
             w = None if weights is None else weights[c0:c1]
             plan.weighted_residual(s, images[c0:c1], w, residual=False, loss=loss)
             del s
@@ -61,7 +61,7 @@ class SliceLossFn(torch.autograd.Function):
         grad = None
         for c0 in range(0, n, chunk):
             c1 = min(n, c0 + chunk)
-            s, _, _ = plan.slice(quats[c0:c1], det_q)
+            s, _ = plan.slice(quats[c0:c1], det_q)
             w = None if weights is None else weights[c0:c1]
             r, _ = plan.weighted_residual(s, images[c0:c1], w, scale=scale, residual=True)
             del s

@@ -443,8 +443,7 @@ int spfel_set_model(spfel_plan plan, const void *model, void *stream) {
 }
 
 int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
-                const float *det_q, int64_t P, void *out, uint16_t *out_bf16,
-                float *out_norm2, void *stream) {
+                const float *det_q, int64_t P, void *out, float *out_norm2, void *stream) {
   clear_error();
   Plan *p = reinterpret_cast<Plan *>(plan);
   if (!live(p)) return fail(SPFEL_ESTATE, "slice: not a live plan");
@@ -461,30 +460,20 @@ int spfel_slice(spfel_plan plan, const float *quats, int64_t M,
                               : hipSuccess;
     return e0 == hipSuccess ? SPFEL_OK : hip_fail(e0, "slice: launch");
   }
-  if (!out && !out_bf16 && !out_norm2) return fail(SPFEL_EINVAL, "slice: no output requested");
-  if (out_bf16 && cplx) return fail(SPFEL_EUNSUPPORTED, "slice: bfloat16 output is REAL-domain only");
+  if (!out && !out_norm2) return fail(SPFEL_EINVAL, "slice: no output requested");
+  if (out_norm2 && !out) return fail(SPFEL_EINVAL, "slice: norms need out");
   if (!quats) return fail(SPFEL_EINVAL, "slice: quats is NULL");
   if (!det_q && P != p->det_P)
     return fail(SPFEL_EINVAL, "slice: det_q is NULL and P differs from the registered detector");
   if (!aligned(quats, 4) || (det_q && !aligned(det_q, 4))) return fail(SPFEL_EINVAL, "slice: input misaligned");
-  if (out && !aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "slice: out misaligned");
-  if (out_bf16 && !aligned(out_bf16, 2)) return fail(SPFEL_EINVAL, "slice: out_bf16 misaligned");
+  if (!aligned(out, cplx ? 8 : 4)) return fail(SPFEL_EINVAL, "slice: out misaligned");
   if (out_norm2 && !aligned(out_norm2, 4)) return fail(SPFEL_EINVAL, "slice: out_norm2 misaligned");
   if (M > (int64_t)1 << 31 || P > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "slice: M or P too large");
-  if (out_norm2 && !out && !out_bf16) return fail(SPFEL_EINVAL, "slice: norms need out or out_bf16");
-  if (out_norm2 && !out && cplx) return fail(SPFEL_EINVAL, "slice: COMPLEX norms need out");
   DeviceGuard g(p->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "slice: hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_interp(*p, quats, M, det_q, P, out, out_bf16, s);
-  if (e == hipSuccess && out_norm2) {
-    if (out && !cplx)
-      e = launch_row_norm2(out, false, M, P, out_norm2, s);
-    else if (out && cplx)
-      e = launch_row_norm2(out, false, M, 2 * P, out_norm2, s);
-    else
-      e = launch_row_norm2(out_bf16, true, M, P, out_norm2, s);
-  }
+  hipError_t e = launch_interp(*p, quats, M, det_q, P, out, s);
+  if (e == hipSuccess && out_norm2) e = launch_row_norm2(out, false, M, cplx ? 2 * P : P, out_norm2, s);
   if (e != hipSuccess) return hip_fail(e, "slice: launch");
   return SPFEL_OK;
 }
@@ -505,11 +494,41 @@ int spfel_row_norm2(const void *x, int dtype, int64_t rows, int64_t cols,
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "row_norm2: launch");
 }
 
+int spfel_column_mean(const float *x, int64_t rows, int64_t cols, int round_to_integer,
+                      float *out, void *stream) {
+  clear_error();
+  if (rows < 1 || cols < 0) return fail(SPFEL_EINVAL, "column_mean: rows must be >= 1, cols >= 0");
+  if (cols == 0) return SPFEL_OK;
+  if (!x || !out) return fail(SPFEL_EINVAL, "column_mean: NULL pointer");
+  if (!aligned(x, 4) || !aligned(out, 4)) return fail(SPFEL_EINVAL, "column_mean: misaligned");
+  if (cols > (int64_t)1 << 31) return fail(SPFEL_ERANGE, "column_mean: too many columns");
+  hipError_t e = launch_column_mean(x, rows, cols, round_to_integer, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "column_mean: launch");
+}
+
+int spfel_bf16_centred(const float *x, int64_t rows, int64_t cols, const float *centre,
+                       uint16_t *out, float *norm2, float *err, void *stream) {
+  clear_error();
+  if (rows < 0 || cols < 0) return fail(SPFEL_EINVAL, "bf16_centred: negative size");
+  if (rows == 0) return SPFEL_OK;
+  if (!norm2 && !err && !out) return fail(SPFEL_EINVAL, "bf16_centred: no output requested");
+  if (!out) return fail(SPFEL_EINVAL, "bf16_centred: out is NULL");
+  if (!x && cols > 0) return fail(SPFEL_EINVAL, "bf16_centred: x is NULL");
+  if ((x && !aligned(x, 4)) || (centre && !aligned(centre, 4)) || !aligned(out, 2) ||
+      (norm2 && !aligned(norm2, 4)) || (err && !aligned(err, 4)))
+    return fail(SPFEL_EINVAL, "bf16_centred: misaligned pointer");
+  if (rows > (int64_t)1 << 31 || cols > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "bf16_centred: size too large");
+  hipError_t e = launch_bf16_centred(x, rows, cols, centre, out, norm2, err, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "bf16_centred: launch");
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode) {
   if (M < 0 || n_img < 0 || P < 0) return 0;
   size_t b = match_f32_workspace_bytes(M, n_img, P);
-  if (mode == SPFEL_MATCH_BF16_RESCORE8 || mode == SPFEL_MATCH_BF16X3_RESCORE8)
-    b = match_bf16_candidate_bytes(M, n_img);
+  if (mode == SPFEL_MATCH_BF16_RESCORE8)
+    b = align256(match_bf16_candidate_bytes(M, n_img)) + match_rescore_bytes(n_img);
   return b < 256 ? 256 : b;
 }
 
@@ -517,12 +536,12 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 const void *images, const float *image_norm2, int64_t M,
                 int64_t n_img, int64_t P, int64_t m_offset, int mode,
                 const float *slices_f32, const float *images_f32,
-                int32_t *best_idx, float *best_dist, void *workspace,
+                const float *slice_err, const float *image_err,
+                int32_t *best_idx, float *best_dist, int32_t *flags, void *workspace,
                 size_t workspace_bytes, void *stream) {
   clear_error();
   if (M < 0 || n_img < 0 || P < 0 || m_offset < 0) return fail(SPFEL_EINVAL, "match: negative size");
-  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8 &&
-      mode != SPFEL_MATCH_BF16X3_RESCORE8)
+  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8)
     return fail(SPFEL_EINVAL, "match: unknown mode");
   if (m_offset + M > 0x7fffffffLL) return fail(SPFEL_ERANGE, "match: model index exceeds int32");
   if (P > (int64_t)1 << 30 || n_img > (int64_t)1 << 30) return fail(SPFEL_ERANGE, "match: size too large");
@@ -530,17 +549,17 @@ int spfel_match(const void *slices, const float *slice_norm2,
   if (!slices || !images || !slice_norm2 || !image_norm2 || !best_idx || !best_dist)
     return fail(SPFEL_EINVAL, "match: NULL pointer");
   const bool bf = mode != SPFEL_MATCH_FP32;
-  const bool x3 = mode == SPFEL_MATCH_BF16X3_RESCORE8;
-  if (bf && (!slices_f32 || !images_f32))
-    return fail(SPFEL_EINVAL, "match: BF16 rescoring needs slices_f32 and images_f32");
+  if (bf && (!slices_f32 || !images_f32 || !slice_err || !image_err))
+    return fail(SPFEL_EINVAL, "match: BF16 mode needs slices_f32, images_f32, slice_err and image_err");
   if (!aligned(slices, bf ? 2 : 4) || !aligned(images, bf ? 2 : 4) || !aligned(slice_norm2, 4) ||
       !aligned(image_norm2, 4) || !aligned(best_idx, 4) || !aligned(best_dist, 4) ||
-      (bf && (!aligned(slices_f32, 4) || !aligned(images_f32, 4))))
+      (bf && (!aligned(slices_f32, 4) || !aligned(images_f32, 4) || !aligned(slice_err, 4) ||
+              !aligned(image_err, 4) || (flags && !aligned(flags, 4)))))
     return fail(SPFEL_EINVAL, "match: misaligned pointer");
   const size_t need = spfel_match_workspace_bytes(M, n_img, P, mode);
   if (!workspace || workspace_bytes < need)
     return fail(SPFEL_EINVAL, "match: workspace smaller than spfel_match_workspace_bytes");
-  if (!aligned(workspace, 16)) return fail(SPFEL_EINVAL, "match: workspace not 16-byte aligned");
+  if (!aligned(workspace, 256)) return fail(SPFEL_EINVAL, "match: workspace not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (!bf) {
@@ -552,40 +571,28 @@ int spfel_match(const void *slices, const float *slice_norm2,
     if (e == hipSuccess) e = launch_unpack_keys(keys, best_idx, best_dist, n_img, s);
   } else {
     auto *cand = static_cast<uint32_t *>(workspace);
+    char *scratch = static_cast<char *>(workspace) + align256(match_bf16_candidate_bytes(M, n_img));
     e = launch_match_bf16(static_cast<const uint16_t *>(slices), static_cast<const uint16_t *>(images),
-                          slice_norm2, image_norm2, M, n_img, P, cand, x3, s);
+                          slice_norm2, image_norm2, M, n_img, P, cand, s);
     if (e == hipSuccess)
-      e = launch_rescore(cand, match_bf16_tile_rows(M, n_img, P, slices, images, x3), M, n_img,
-                         P, m_offset, slices_f32, images_f32, slice_norm2, image_norm2, best_idx,
-                         best_dist, s);
+      e = launch_rescore(cand, match_bf16_tile_rows(M, n_img, P, slices, images), M, n_img, P,
+                         m_offset, slices_f32, images_f32, slice_norm2, image_norm2, slice_err,
+                         image_err, best_idx, best_dist, flags, scratch, s);
   }
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "match: launch");
 }
 
-int spfel_split_bf16(const float *x, int64_t n, uint16_t *out, void *stream) {
-  clear_error();
-  if (n < 0) return fail(SPFEL_EINVAL, "split_bf16: negative size");
-  if (n == 0) return SPFEL_OK;
-  if (!x || !out) return fail(SPFEL_EINVAL, "split_bf16: NULL pointer");
-  if (!aligned(x, 4) || !aligned(out, 2)) return fail(SPFEL_EINVAL, "split_bf16: misaligned");
-  hipError_t e = launch_split_bf16(x, n, out, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "split_bf16: launch");
-}
-
-
 // Slice buffers of one pipeline stage, carved from the caller's workspace.
 struct OrientStage {
   float *f32 = nullptr;      // chunk x P
-  uint16_t *b16 = nullptr;   // chunk x P (BF16) or 2 x chunk x P (BF16X3)
-  float *norm = nullptr;     // chunk
+  uint16_t *b16 = nullptr;   // chunk x P centred BF16 (BF16 mode)
+  float *norm = nullptr;     // chunk: float32 norms (FP32 mode) or BF16 norms
+  float *err = nullptr;      // chunk: rounding-error norms (BF16 mode)
 };
-
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static size_t orient_stage_bytes(int64_t chunk, int64_t P, int mode) {
   size_t b = align256((size_t)chunk * P * sizeof(float));
-  if (mode == SPFEL_MATCH_BF16_RESCORE8) b += align256((size_t)chunk * P * 2);
-  if (mode == SPFEL_MATCH_BF16X3_RESCORE8) b += align256((size_t)chunk * P * 4);
+  if (mode == SPFEL_MATCH_BF16_RESCORE8) b += align256((size_t)chunk * P * 2) + align256((size_t)chunk * sizeof(float));
   b += align256((size_t)chunk * sizeof(float));
   return b;
 }
@@ -605,7 +612,8 @@ size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P, int
 
 int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *det_q, int64_t P,
                  const void *images, const float *image_norm2, const float *images_f32,
-                 int64_t n_img, int mode, int64_t chunk, int32_t *best_idx, float *best_dist,
+                 const float *image_err, const float *centre, int64_t n_img, int mode,
+                 int64_t chunk, int32_t *best_idx, float *best_dist, int32_t *flags,
                  void *workspace, size_t workspace_bytes, void *stream, void *aux_stream) {
   clear_error();
   Plan *p = reinterpret_cast<Plan *>(plan);
@@ -614,8 +622,7 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
   if (p->domain != SPFEL_REAL) return fail(SPFEL_EUNSUPPORTED, "orient: REAL plans only");
   if (M < 0 || P < 0 || n_img < 0) return fail(SPFEL_EINVAL, "orient: negative size");
   if (chunk <= 0) return fail(SPFEL_EINVAL, "orient: chunk must be positive");
-  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8 &&
-      mode != SPFEL_MATCH_BF16X3_RESCORE8)
+  if (mode != SPFEL_MATCH_FP32 && mode != SPFEL_MATCH_BF16_RESCORE8)
     return fail(SPFEL_EINVAL, "orient: unknown mode");
   if (M == 0 || n_img == 0) return SPFEL_OK;
   if (P == 0) return fail(SPFEL_EINVAL, "orient: P must be positive");
@@ -623,8 +630,10 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
     return fail(SPFEL_EINVAL, "orient: det_q is NULL and P differs from the registered detector");
   if (!quats || !images || !image_norm2 || !best_idx || !best_dist)
     return fail(SPFEL_EINVAL, "orient: NULL pointer");
-  if (mode != SPFEL_MATCH_FP32 && !images_f32)
-    return fail(SPFEL_EINVAL, "orient: BF16 modes need images_f32");
+  const bool bf = mode == SPFEL_MATCH_BF16_RESCORE8;
+  if (bf && (!images_f32 || !image_err))
+    return fail(SPFEL_EINVAL, "orient: BF16 mode needs images_f32 and image_err");
+  if (bf && centre && !aligned(centre, 4)) return fail(SPFEL_EINVAL, "orient: centre misaligned");
   if (m_offset_overflow(M)) return fail(SPFEL_ERANGE, "orient: model index exceeds int32");
   if (chunk > M) chunk = M;
   const size_t need = spfel_orient_workspace_bytes(chunk, n_img, P, mode);
@@ -634,7 +643,6 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
   if (g.err != hipSuccess) return hip_fail(g.err, "orient: hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipStream_t a = static_cast<hipStream_t>(aux_stream);
-  if (a == s) a = s;  // one stream: the stages simply run in order
   char *ws = static_cast<char *>(workspace);
   OrientStage st[2];
   const size_t sb = orient_stage_bytes(chunk, P, mode);
@@ -642,9 +650,11 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
     char *b = ws + k * sb;
     st[k].f32 = reinterpret_cast<float *>(b);
     b += align256((size_t)chunk * P * sizeof(float));
-    if (mode != SPFEL_MATCH_FP32) {
+    if (bf) {
       st[k].b16 = reinterpret_cast<uint16_t *>(b);
-      b += align256((size_t)chunk * P * (mode == SPFEL_MATCH_BF16X3_RESCORE8 ? 4 : 2));
+      b += align256((size_t)chunk * P * 2);
+      st[k].err = reinterpret_cast<float *>(b);
+      b += align256((size_t)chunk * sizeof(float));
     }
     st[k].norm = reinterpret_cast<float *>(b);
   }
@@ -663,23 +673,20 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
       e = hipStreamWaitEvent(a, p->ev_matched[k], 0);
       if (e != hipSuccess) return hip_fail(e, "orient: event");
     }
-    uint16_t *b16 = mode == SPFEL_MATCH_BF16_RESCORE8 ? st[k].b16 : nullptr;
-    rc = spfel_slice(plan, quats + 4 * m0, mc, det_q, P, st[k].f32, b16, st[k].norm, a);
+    rc = spfel_slice(plan, quats + 4 * m0, mc, det_q, P, st[k].f32, bf ? nullptr : st[k].norm, a);
     if (rc != SPFEL_OK) return rc;
-    if (mode == SPFEL_MATCH_BF16X3_RESCORE8) {
-      // planes of this chunk: hi at [0, mc P), lo at [mc P, 2 mc P)
-      rc = spfel_split_bf16(st[k].f32, mc * P, st[k].b16, a);
+    if (bf) {
+      rc = spfel_bf16_centred(st[k].f32, mc, P, centre, st[k].b16, st[k].norm, st[k].err, a);
       if (rc != SPFEL_OK) return rc;
     }
     e = hipEventRecord(p->ev_sliced[k], a);
     if (e == hipSuccess && a != s) e = hipStreamWaitEvent(s, p->ev_sliced[k], 0);
     if (e != hipSuccess) return hip_fail(e, "orient: event");
     // match stage on the caller's stream
-    const void *sl = mode == SPFEL_MATCH_FP32 ? static_cast<const void *>(st[k].f32)
-                                              : static_cast<const void *>(st[k].b16);
+    const void *sl = bf ? static_cast<const void *>(st[k].b16) : static_cast<const void *>(st[k].f32);
     rc = spfel_match(sl, st[k].norm, images, image_norm2, mc, n_img, P, m0, mode,
-                     mode == SPFEL_MATCH_FP32 ? nullptr : st[k].f32, images_f32, best_idx,
-                     best_dist, mws, mws_bytes, s);
+                     bf ? st[k].f32 : nullptr, images_f32, bf ? st[k].err : nullptr, image_err,
+                     best_idx, best_dist, flags, mws, mws_bytes, s);
     if (rc != SPFEL_OK) return rc;
     e = hipEventRecord(p->ev_matched[k], s);
     if (e != hipSuccess) return hip_fail(e, "orient: event");

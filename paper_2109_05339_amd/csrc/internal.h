@@ -82,8 +82,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // detq == nullptr selects the plan's registered detector (tiled kernel).
 hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M,
-                         const float *detq, int64_t P, void *out,
-                         uint16_t *out_bf16, hipStream_t s);
+                         const float *detq, int64_t P, void *out, hipStream_t s);
 hipError_t launch_row_norm2(const void *x, bool bf16, int64_t rows,
                             int64_t cols, float *out, hipStream_t s);
 
@@ -104,22 +103,30 @@ size_t match_f32_workspace_bytes(int64_t M, int64_t N, int64_t P);
 hipError_t launch_match_f32(const float *S, const float *D, const float *sn,
                             const float *dn, int64_t M, int64_t N, int64_t P,
                             int64_t m_offset, void *workspace, hipStream_t s);
-// x3: S and D are [2][rows][P] (hi, lo) planes.  The candidate buffer
-// holds 8 words per image per tile of tile_rows model images (128 or 256,
-// match_bf16_tile_rows); its size is that of the 128-row tiling.
-int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D,
-                         bool x3);
+// The candidate buffer holds 8 words per image per tile of tile_rows model
+// images (128 or 256, match_bf16_tile_rows); its size is that of the
+// 128-row tiling.
+int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D);
 size_t match_bf16_candidate_bytes(int64_t M, int64_t N);
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D,
                              const float *sn, const float *dn, int64_t M,
-                             int64_t N, int64_t P, uint32_t *cand, bool x3,
-                             hipStream_t s);
+                             int64_t N, int64_t P, uint32_t *cand, hipStream_t s);
+// Certified rescore and fallback of the BF16 matcher.  scratch:
+// match_rescore_bytes(N) bytes, 256-byte aligned (chunk maxima, fallback
+// count, list and keys).
+size_t match_rescore_bytes(int64_t N);
 hipError_t launch_rescore(const uint32_t *cand, int tile_rows, int64_t M, int64_t N,
                           int64_t P, int64_t m_offset, const float *S32,
                           const float *D32, const float *sn, const float *dn,
-                          int32_t *best_idx, float *best_dist, hipStream_t s);
-hipError_t launch_split_bf16(const float *x, int64_t n, uint16_t *out,
-                             hipStream_t s);
+                          const float *se, const float *de, int32_t *best_idx,
+                          float *best_dist, int32_t *flags, void *scratch,
+                          hipStream_t s);
+// Matcher operands (centre.hip).
+hipError_t launch_column_mean(const float *x, int64_t rows, int64_t cols,
+                              int round_int, float *out, hipStream_t s);
+hipError_t launch_bf16_centred(const float *x, int64_t rows, int64_t cols,
+                               const float *c, uint16_t *out, float *norm2,
+                               float *err, hipStream_t s);
 
 hipError_t launch_residual(bool cplx, const void *s, const void *d,
                            const float *w, int64_t count, float scale,

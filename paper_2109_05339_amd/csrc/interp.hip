@@ -25,8 +25,7 @@ __global__ __launch_bounds__(256) void rotation_kernel(const float *__restrict__
 template <int W, bool CPLX>
 __global__ __launch_bounds__(256) void interp_gather_kernel(
     const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
-    const float *__restrict__ detq, int64_t P, void *__restrict__ out_,
-    uint16_t *__restrict__ out_bf16) {
+    const float *__restrict__ detq, int64_t P, void *__restrict__ out_) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * P) return;
   const int64_t m = idx / P;
@@ -47,7 +46,6 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
       if (out_) static_cast<float2 *>(out_)[idx] = make_float2(nan, nan);
     } else {
       if (out_) static_cast<float *>(out_)[idx] = nan;
-      if (out_bf16) out_bf16[idx] = 0x7fc0u;
     }
     return;
   }
@@ -112,7 +110,6 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
       s = fmaf(w0[a], pr, s);
     }
     if (out_) static_cast<float *>(out_)[idx] = s;
-    if (out_bf16) out_bf16[idx] = f32_to_bf16(s);
   }
 }
 
@@ -145,7 +142,7 @@ template <int W, bool CPLX>
 __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
     const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
-    void *__restrict__ out_, uint16_t *__restrict__ out_bf16) {
+    void *__restrict__ out_) {
   typedef typename std::conditional<CPLX, float2, float>::type T;
   constexpr int kCap = brick_bytes<CPLX>() / (int)sizeof(T);
   __shared__ __attribute__((aligned(16))) T brick[kCap];
@@ -342,7 +339,6 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
       if (out_) static_cast<float2 *>(out_)[o] = make_float2(nan, nan);
     } else {
       if (out_) static_cast<float *>(out_)[o] = nan;
-      if (out_bf16) out_bf16[o] = 0x7fc0u;
     }
     return;
   }
@@ -408,13 +404,12 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
     if (out_) static_cast<float2 *>(out_)[o] = make_float2(sr, si);
   } else {
     if (out_) static_cast<float *>(out_)[o] = sr;
-    if (out_bf16) out_bf16[o] = f32_to_bf16(sr);
   }
 }
 
 template <int W>
 static hipError_t interp_w(const Plan &pl, const double *rot, int64_t M, const float *detq,
-                           int64_t P, void *out, uint16_t *out_bf16, hipStream_t s) {
+                           int64_t P, void *out, hipStream_t s) {
   const bool cplx = pl.domain == SPFEL_COMPLEX;
   if (detq == nullptr) {
     const int tiles = (int)((P + kTile - 1) / kTile);
@@ -423,28 +418,28 @@ static hipError_t interp_w(const Plan &pl, const double *rot, int64_t M, const f
     if (cplx)
       hipLaunchKernelGGL((interp_tiled_kernel<W, true>), dim3((unsigned)blocks), dim3(kTile), 0, s,
                          pl.u, pl.nf, (float)pl.beta, rot, M, pl.det_sorted, pl.det_perm, P,
-                         tiles, out, out_bf16);
+                         tiles, out);
     else
       hipLaunchKernelGGL((interp_tiled_kernel<W, false>), dim3((unsigned)blocks), dim3(kTile), 0,
                          s, pl.u, pl.nf, (float)pl.beta, rot, M, pl.det_sorted, pl.det_perm, P,
-                         tiles, out, out_bf16);
+                         tiles, out);
     return hipGetLastError();
   }
   const int64_t total = M * P;
   const dim3 grid((unsigned)((total + 255) / 256)), block(256);
   if (cplx)
     hipLaunchKernelGGL((interp_gather_kernel<W, true>), grid, block, 0, s, pl.u, pl.nf,
-                       (float)pl.beta, rot, M, detq, P, out, out_bf16);
+                       (float)pl.beta, rot, M, detq, P, out);
   else
     hipLaunchKernelGGL((interp_gather_kernel<W, false>), grid, block, 0, s, pl.u, pl.nf,
-                       (float)pl.beta, rot, M, detq, P, out, out_bf16);
+                       (float)pl.beta, rot, M, detq, P, out);
   return hipGetLastError();
 }
 
 // Orientations go in batches of kRotCap: each batch's scaled rotations are
 // computed into the plan's table, then its points are interpolated.
 hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M, const float *detq,
-                         int64_t P, void *out, uint16_t *out_bf16, hipStream_t s) {
+                         int64_t P, void *out, hipStream_t s) {
   const size_t el = pl.domain == SPFEL_COMPLEX ? 8 : 4;
   const double scale = (double)pl.nf / (2.0 * M_PI);
   for (int64_t m0 = 0; m0 < M; m0 += kRotCap) {
@@ -454,13 +449,12 @@ hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M, const fl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void *o = out ? static_cast<char *>(out) + (size_t)m0 * P * el : nullptr;
-    uint16_t *ob = out_bf16 ? out_bf16 + (size_t)m0 * P : nullptr;
     switch (pl.w) {
-      case 4: e = interp_w<4>(pl, pl.rot, mc, detq, P, o, ob, s); break;
-      case 5: e = interp_w<5>(pl, pl.rot, mc, detq, P, o, ob, s); break;
-      case 6: e = interp_w<6>(pl, pl.rot, mc, detq, P, o, ob, s); break;
-      case 7: e = interp_w<7>(pl, pl.rot, mc, detq, P, o, ob, s); break;
-      default: e = interp_w<8>(pl, pl.rot, mc, detq, P, o, ob, s); break;
+      case 4: e = interp_w<4>(pl, pl.rot, mc, detq, P, o, s); break;
+      case 5: e = interp_w<5>(pl, pl.rot, mc, detq, P, o, s); break;
+      case 6: e = interp_w<6>(pl, pl.rot, mc, detq, P, o, s); break;
+      case 7: e = interp_w<7>(pl, pl.rot, mc, detq, P, o, s); break;
+      default: e = interp_w<8>(pl, pl.rot, mc, detq, P, o, s); break;
     }
     if (e != hipSuccess) return e;
   }

@@ -7,9 +7,12 @@
 //   FP32: v_mfma_f32_32x32x2_f32, per-tile column argmin, then a 64-bit
 //         atomicMin of (order-preserving distance key << 32 | model index),
 //         so the lowest index wins ties across tiles and across calls.
-//   BF16: v_mfma_f32_32x32x16_bf16 with float32 accumulation, per-tile column
-//         top-8 of the proxy distance; a second kernel merges the tiles'
-//         candidates per image and rescores the 8 in float32.
+//   BF16: v_mfma_f32_32x32x16_bf16 with float32 accumulation on centred,
+//         rounded operands, per-tile column top-8 of the proxy distance; a
+//         second kernel merges the tiles' candidates per image, rescores in
+//         float32 those whose lower bound can beat the running best, and
+//         certifies that no other model image can; images it cannot
+//         certify are matched again against every model image in float32.
 #include "device_common.h"
 #include "internal.h"
 
@@ -366,9 +369,8 @@ __device__ inline void insert8(unsigned long long (&top)[8], unsigned long long 
 // rounds of the chip's 256 resident blocks, P is a whole number of its
 // 64-wide K steps and both operands are 16-byte aligned; otherwise
 // 128 x 128 tiles.
-int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D,
-                         bool x3) {
-  if (x3 || P % 64 != 0 || !al16(S) || !al16(D)) return 128;
+int match_bf16_tile_rows(int64_t M, int64_t N, int64_t P, const void *S, const void *D) {
+  if (P % 64 != 0 || !al16(S) || !al16(D)) return 128;
   const int64_t big = ((M + 255) / 256) * ((N + 255) / 256);
   return big >= 4 * 256 ? 256 : 128;
 }
@@ -380,22 +382,16 @@ size_t match_bf16_candidate_bytes(int64_t M, int64_t N) {
 }
 
 // Candidate word: proxy-distance key with its 7 low bits replaced by the
-// row within the tile (a relative perturbation below 2^-16 of the proxy).
-// X3: S and D are [2][rows][P] planes (hi, lo) with hi + lo the float32
-// value to about 2^-16; the products hi.hi + lo.hi + hi.lo (lo.lo dropped)
-// run on the same BF16 matrix cores, three MFMAs per step.
-template <bool X3>
+// row within the tile (a relative perturbation below 2^-15 of the proxy;
+// clearing or setting those bits bounds the proxy from below or above).
 __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
     const uint16_t *__restrict__ S, const uint16_t *__restrict__ D, const float *__restrict__ sn,
     const float *__restrict__ dn, int64_t M, int64_t N, int64_t P, uint32_t *__restrict__ cand,
     int tiles_m, int tiles_n, int vec) {
-  constexpr int kPlanes = X3 ? 2 : 1;
-  constexpr int kBKx = X3 ? 32 : kBKH;     // bf16 values of P per K step
-  constexpr int kLdx = kBKx + 8;           // LDS row stride
-  constexpr int kSeg = kBKx / 8;           // 16-byte segments per row and step
+  constexpr int kSeg = kBKH / 8;           // 16-byte segments per row and step
   constexpr int kLoads = kBM * kSeg / 256; // segments per thread and operand
-  __shared__ __attribute__((aligned(16))) uint16_t As[kPlanes][kBM * kLdx];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kPlanes][kBN * kLdx];
+  __shared__ __attribute__((aligned(16))) uint16_t As[kBM * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN * kLdH];
   __shared__ float sns[kBM], dns[kBN];
   __shared__ uint32_t red[2][kBN][8];
 
@@ -405,16 +401,14 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
 
-  uint4 ra[kPlanes][kLoads], rb[kPlanes][kLoads];
+  uint4 ra[kLoads], rb[kLoads];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int pl = 0; pl < kPlanes; ++pl)
-#pragma unroll
-      for (int i = 0; i < kLoads; ++i) {
-        const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
-        ra[pl][i] = load_row8h(S + pl * M * P, M, row0 + r, P, k0 + c, vec);
-        rb[pl][i] = load_row8h(D + pl * N * P, N, col0 + r, P, k0 + c, vec);
-      }
+    for (int i = 0; i < kLoads; ++i) {
+      const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
+      ra[i] = load_row8h(S, M, row0 + r, P, k0 + c, vec);
+      rb[i] = load_row8h(D, N, col0 + r, P, k0 + c, vec);
+    }
   };
 
   floatx16 acc[2][2];
@@ -426,40 +420,30 @@ __global__ __launch_bounds__(256, 2) void match_bf16_kernel(
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   gload(0);
-  for (int64_t k0 = 0; k0 < P; k0 += kBKx) {
+  for (int64_t k0 = 0; k0 < P; k0 += kBKH) {
     __syncthreads();
 #pragma unroll
-    for (int pl = 0; pl < kPlanes; ++pl)
-#pragma unroll
-      for (int i = 0; i < kLoads; ++i) {
-        const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
-        *reinterpret_cast<uint4 *>(&As[pl][r * kLdx + c]) = ra[pl][i];
-        *reinterpret_cast<uint4 *>(&Bs[pl][r * kLdx + c]) = rb[pl][i];
-      }
+    for (int i = 0; i < kLoads; ++i) {
+      const int id = tid + 256 * i, r = id / kSeg, c = (id % kSeg) * 8;
+      *reinterpret_cast<uint4 *>(&As[r * kLdH + c]) = ra[i];
+      *reinterpret_cast<uint4 *>(&Bs[r * kLdH + c]) = rb[i];
+    }
     __syncthreads();
-    if (k0 + kBKx < P) gload(k0 + kBKx);
+    if (k0 + kBKH < P) gload(k0 + kBKH);
 #pragma unroll
-    for (int kk = 0; kk < kBKx / 16; ++kk) {
-      bf16x8 a[kPlanes][2], b[kPlanes][2];
+    for (int kk = 0; kk < kBKH / 16; ++kk) {
+      bf16x8 a[2], b[2];
 #pragma unroll
-      for (int pl = 0; pl < kPlanes; ++pl) {
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 64 + i * 32 + lr) * kLdH + kk * 16 + lh * 8]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-          a[pl][i] = *reinterpret_cast<const bf16x8 *>(&As[pl][(wm * 64 + i * 32 + lr) * kLdx + kk * 16 + lh * 8]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          b[pl][j] = *reinterpret_cast<const bf16x8 *>(&Bs[pl][(wn * 64 + j * 32 + lr) * kLdx + kk * 16 + lh * 8]);
-      }
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 64 + j * 32 + lr) * kLdH + kk * 16 + lh * 8]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (X3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[kPlanes - 1][j], acc[i][j], 0, 0, 0);
-          }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
 
@@ -692,17 +676,9 @@ __global__ __launch_bounds__(512, 1) void match_bf16_big_kernel(
 
 hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *sn,
                              const float *dn, int64_t M, int64_t N, int64_t P, uint32_t *cand,
-                             bool x3, hipStream_t s) {
+                             hipStream_t s) {
   const int vec = (P % 8 == 0) && al16(S) && al16(D);
-  if (x3) {
-    const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
-    const int64_t blocks = (int64_t)tiles_m * tiles_n;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(match_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn,
-                       dn, M, N, P, cand, tiles_m, tiles_n, vec);
-    return hipGetLastError();
-  }
-  if (match_bf16_tile_rows(M, N, P, S, D, false) == 256) {
+  if (match_bf16_tile_rows(M, N, P, S, D) == 256) {
     const int tiles_m = (int)((M + kBM2 - 1) / kBM2), tiles_n = (int)((N + kBN2 - 1) / kBN2);
     const int64_t blocks = (int64_t)tiles_m * tiles_n;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -713,24 +689,117 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
   const int tiles_m = (int)((M + kBM - 1) / kBM), tiles_n = (int)((N + kBN - 1) / kBN);
   const int64_t blocks = (int64_t)tiles_m * tiles_n;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(match_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
+  hipLaunchKernelGGL(match_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, S, D, sn, dn, M,
                      N, P, cand, tiles_m, tiles_n, vec);
   return hipGetLastError();
 }
 
-// One wavefront per image: merge every tile's 8 candidates into the image's
-// 8 smallest proxies (ties: lowest model index), rescore those 8 exactly in
-// float32 against the float32 slices and image, and fold the best into the
-// caller's running (best_dist, best_idx).
+// Bounds of the certified rescore (float32 arithmetic; every bound carries
+// a relative margin of 2^-16, far above the few roundings in its formula).
+//   proxy b~ = |s^|^2 + |d^|^2 - 2 s^.d^ computed on the matrix cores;
+//     |b~ - |s^ - d^|^2| <= A = g_acc (|s^| + |d^|)^2, g_acc = gamma_{P+64}
+//     at u = 2^-23 (every product added with its own rounding, whatever the
+//     hardware's internal order and rounding mode);
+//   true distance D = |s - d|^2:  |sqrt(D) - |s^ - d^|| <= e_m + f_n;
+//   float32 rescore D~ of D (direct sum of (s - d)^2, chains of at most
+//     P/64 + 16 roundings):  |D~ - D| <= g_run D.
+struct CertBounds {
+  float g_acc, g_run;
+};
+constexpr float kLo = 1.0f - 0x1p-16f, kHi = 1.0f + 0x1p-16f;
+
+__device__ inline float lower_sqrt_dist(float b_lo, float A, float ef) {
+  return sqrtf(fmaxf(b_lo - A, 0.f)) * kLo - ef * kHi;
+}
+__device__ inline float upper_sqrt_dist(float b_hi, float A, float ef) {
+  return sqrtf(fmaxf(b_hi, 0.f) + A) * kHi + ef * kHi;
+}
+// sqrt of the largest exact distance a float32 rescored value d can stand for
+__device__ inline float upper_sqrt_rescored(float d, float g_run) {
+  return sqrtf(d * (1.0f + 2.0f * g_run)) * kHi;
+}
+
+// Sum over p of (s_p - d_p)^2 for one lane's share of a row (float32).
+__device__ inline float direct_part(const float *__restrict__ srow, const float *__restrict__ drow,
+                                    int64_t P, int lane, int vec) {
+  float acc = 0.f;
+  if (vec) {
+    const float4 *s4 = reinterpret_cast<const float4 *>(srow);
+    const float4 *d4 = reinterpret_cast<const float4 *>(drow);
+    for (int64_t q = lane; q < P / 4; q += 64) {
+      const float4 a = s4[q], b = d4[q];
+      float t;
+      t = a.x - b.x; acc = fmaf(t, t, acc);
+      t = a.y - b.y; acc = fmaf(t, t, acc);
+      t = a.z - b.z; acc = fmaf(t, t, acc);
+      t = a.w - b.w; acc = fmaf(t, t, acc);
+    }
+  } else {
+    for (int64_t p = lane; p < P; p += 64) {
+      const float t = srow[p] - drow[p];
+      acc = fmaf(t, t, acc);
+    }
+  }
+  return acc;
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Chunk maxima the certificate needs: max_m |s^_m| and max_m e_m.
+__global__ __launch_bounds__(1024) void chunk_stats_kernel(const float *__restrict__ sn,
+                                                           const float *__restrict__ se, int64_t M,
+                                                           float *__restrict__ stats) {
+  __shared__ float sh[2][1024];
+  float a = 0.f, b = 0.f;
+  for (int64_t m = threadIdx.x; m < M; m += 1024) {
+    a = fmaxf(a, sqrtf(fmaxf(sn[m], 0.f)));
+    b = fmaxf(b, se[m]);
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sh[0][threadIdx.x] = fmaxf(sh[0][threadIdx.x], sh[0][threadIdx.x + st]);
+      sh[1][threadIdx.x] = fmaxf(sh[1][threadIdx.x], sh[1][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = sh[0][0];
+    stats[1] = sh[1][0];
+  }
+}
+
+// One wavefront per image:
+//  1. merge every tile's 8 candidates into the image's 8 smallest proxies
+//     (ties: lowest model index);
+//  2. bound each candidate's true distance from below and above;
+//  3. rescore in float32 (direct sum of squared differences) exactly the
+//     candidates whose lower bound does not exceed both the running best
+//     and the smallest upper bound among the 8 (no other candidate can be
+//     the minimiser), and fold the best into (best_dist, best_idx);
+//  4. certify the image: every model image outside the 8 has a true
+//     distance at least the 8th proxy's lower bound (with the chunk's
+//     largest norm and rounding error); if that bound does not exceed the
+//     running best, the image goes on the fallback list (and flags[n] |= 1)
+//     with its running best as the fallback's starting key.
 __global__ __launch_bounds__(256) void rescore_kernel(
-    const uint32_t *__restrict__ cand, int tiles_m, int tile_rows, int64_t N, int64_t P,
-    uint32_t m_offset,
-    const float *__restrict__ S32, const float *__restrict__ D32, const float *__restrict__ sn,
-    const float *__restrict__ dn, int32_t *__restrict__ best_idx, float *__restrict__ best_dist,
-    int vec) {
+    const uint32_t *__restrict__ cand, int tiles_m, int tile_rows, int64_t M, int64_t N, int64_t P,
+    uint32_t m_offset, const float *__restrict__ S32, const float *__restrict__ D32,
+    const float *__restrict__ sn, const float *__restrict__ dn, const float *__restrict__ se,
+    const float *__restrict__ de, const float *__restrict__ stats, CertBounds cb,
+    int32_t *__restrict__ best_idx, float *__restrict__ best_dist, int32_t *__restrict__ flags,
+    unsigned *__restrict__ fb_count, int32_t *__restrict__ fb_list,
+    unsigned long long *__restrict__ fb_keys, int vec) {
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= N) return;
+  const uint32_t low = (uint32_t)tile_rows - 1u;
   unsigned long long top[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) top[s] = ~0ull;
@@ -739,7 +808,6 @@ __global__ __launch_bounds__(256) void rescore_kernel(
     const int t = c >> 3, s = c & 7;
     const uint32_t k = cand[((int64_t)t * N + n) * 8 + s];
     if (k != ~0u) {
-      const uint32_t low = (uint32_t)tile_rows - 1u;
       const uint32_t m = (uint32_t)t * (uint32_t)tile_rows + (k & low);
       insert8(top, ((unsigned long long)(k & ~low) << 32) | m);
     }
@@ -752,90 +820,151 @@ __global__ __launch_bounds__(256) void rescore_kernel(
 #pragma unroll
     for (int s = 0; s < 8; ++s) insert8(top, other[s]);
   }
+  const float nd = sqrtf(fmaxf(dn[n], 0.f)), fd = de[n];
   int mi[8];
   bool valid[8];
+  float lb[8];
+  float ub_min = __builtin_inff();
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     valid[s] = top[s] != ~0ull;
     mi[s] = valid[s] ? (int)(uint32_t)(top[s] & 0xffffffffu) : 0;
+    const uint32_t key = (uint32_t)(top[s] >> 32);
+    const float ns = sqrtf(fmaxf(sn[mi[s]], 0.f));
+    const float A = cb.g_acc * (ns + nd) * (ns + nd);
+    const float ef = se[mi[s]] + fd;
+    lb[s] = lower_sqrt_dist(key_float(key), A, ef);
+    if (valid[s]) ub_min = fminf(ub_min, upper_sqrt_dist(key_float(key | low), A, ef));
   }
-  float dot[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) dot[s] = 0.f;
-  const float *dimg = D32 + n * P;
-  if (vec) {
-    const int64_t P4 = P / 4;
-    for (int64_t q = lane; q < P4; q += 64) {
-      const float4 d = reinterpret_cast<const float4 *>(dimg)[q];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const float4 v = reinterpret_cast<const float4 *>(S32 + (int64_t)mi[s] * P)[q];
-        dot[s] = fmaf(v.x, d.x, dot[s]);
-        dot[s] = fmaf(v.y, d.y, dot[s]);
-        dot[s] = fmaf(v.z, d.z, dot[s]);
-        dot[s] = fmaf(v.w, d.w, dot[s]);
-      }
-    }
-  } else {
-    for (int64_t p = lane; p < P; p += 64) {
-      const float d = dimg[p];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) dot[s] = fmaf(S32[(int64_t)mi[s] * P + p], d, dot[s]);
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int s = 0; s < 8; ++s) dot[s] += __shfl_xor(dot[s], off);
-  unsigned long long best = ~0ull;
-  const float dnn = dn[n];
+  const float run = best_dist[n];
+  const int32_t run_i = best_idx[n];
+  const float thr = fminf(ub_min, upper_sqrt_rescored(run, cb.g_run));
+  bool take[8];
+  bool any = false;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    if (valid[s]) {
-      const float d = fmaf(-2.0f, dot[s], sn[mi[s]] + dnn);
+    take[s] = valid[s] && lb[s] <= thr;
+    any = any || take[s];
+  }
+  unsigned long long best = ~0ull;
+  if (any) {
+    const float *drow = D32 + n * P;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (take[s]) {   // wavefront-uniform
+        const float d = wave_sum(direct_part(S32 + (int64_t)mi[s] * P, drow, P, lane, vec));
+        const unsigned long long key =
+            ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)mi[s]);
+        best = key < best ? key : best;
+      }
+    }
+  }
+  const unsigned long long run_key = ((unsigned long long)float_key(run) << 32) | (uint32_t)run_i;
+  const unsigned long long now = best < run_key ? best : run_key;
+  // certificate: only needed when model images lie outside the 8
+  bool cert = true;
+  if (M > 8) {
+    const float A8 = cb.g_acc * (stats[0] + nd) * (stats[0] + nd);
+    const float lb8 = lower_sqrt_dist(key_float((uint32_t)(top[7] >> 32)), A8, stats[1] + fd);
+    cert = lb8 > upper_sqrt_rescored(key_float((uint32_t)(now >> 32)), cb.g_run);
+  }
+  if (lane == 0) {
+    if (now != run_key) {
+      best_idx[n] = (int32_t)(uint32_t)(now & 0xffffffffu);
+      best_dist[n] = key_float((uint32_t)(now >> 32));
+    }
+    if (!cert) {
+      if (flags) flags[n] |= 1;
+      const unsigned pos = atomicAdd(fb_count, 1u);
+      fb_list[pos] = (int32_t)n;
+      fb_keys[pos] = now;
+    }
+  }
+}
+
+// Fallback for uncertified images: each work item is (listed image, slab of
+// 64 model images); the block's four wavefronts rescore 16 rows each in
+// float32 (direct sums, as in the rescore) and fold their minimum into the
+// image's key with a 64-bit atomicMin (lowest index on ties).  The number
+// of listed images is read on the device; every block leaves the loop when
+// the work items run out (none when every image was certified).
+__global__ __launch_bounds__(256) void fallback_kernel(
+    const float *__restrict__ S32, const float *__restrict__ D32, int64_t M, int64_t P,
+    uint32_t m_offset, const unsigned *__restrict__ fb_count, const int32_t *__restrict__ fb_list,
+    unsigned long long *__restrict__ fb_keys, int vec) {
+  __shared__ unsigned long long red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t slabs = (M + 63) / 64;
+  const int64_t items = (int64_t)(*fb_count) * slabs;
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const int64_t pos = w / slabs, slab = w - pos * slabs;
+    const int64_t n = fb_list[pos];
+    const float *drow = D32 + n * P;
+    unsigned long long best = ~0ull;
+    for (int r = 0; r < 16; ++r) {
+      const int64_t m = slab * 64 + wave * 16 + r;
+      if (m >= M) break;   // wavefront-uniform
+      const float d = wave_sum(direct_part(S32 + m * P, drow, P, lane, vec));
       const unsigned long long key =
-          ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)mi[s]);
+          ((unsigned long long)float_key(d) << 32) | (uint32_t)(m_offset + (uint32_t)m);
       best = key < best ? key : best;
     }
-  }
-  if (lane == 0 && best != ~0ull) {
-    const unsigned long long run =
-        ((unsigned long long)float_key(best_dist[n]) << 32) | (uint32_t)best_idx[n];
-    if (best < run) {
-      best_idx[n] = (int32_t)(uint32_t)(best & 0xffffffffu);
-      best_dist[n] = key_float((uint32_t)(best >> 32));
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long k = red[0];
+#pragma unroll
+      for (int i = 1; i < 4; ++i) k = red[i] < k ? red[i] : k;
+      if (k != ~0ull) atomicMin(fb_keys + pos, k);
     }
+    __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void fallback_unpack_kernel(
+    const unsigned *__restrict__ fb_count, const int32_t *__restrict__ fb_list,
+    const unsigned long long *__restrict__ fb_keys, int32_t *__restrict__ best_idx,
+    float *__restrict__ best_dist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)(*fb_count)) return;
+  const int32_t n = fb_list[i];
+  const unsigned long long k = fb_keys[i];
+  best_idx[n] = (int32_t)(uint32_t)(k & 0xffffffffu);
+  best_dist[n] = key_float((uint32_t)(k >> 32));
+}
+
+static double gamma_of(double L, double u) { return L * u / (1.0 - L * u); }
+
+size_t match_rescore_bytes(int64_t N) {
+  // stats (2 floats) and the fallback count, then the list and the keys
+  return 256 + (((size_t)N * 4 + 255) & ~(size_t)255) + (size_t)N * 8;
 }
 
 hipError_t launch_rescore(const uint32_t *cand, int tile_rows, int64_t M, int64_t N, int64_t P,
                           int64_t m_offset, const float *S32, const float *D32, const float *sn,
-                          const float *dn, int32_t *best_idx, float *best_dist, hipStream_t s) {
+                          const float *dn, const float *se, const float *de, int32_t *best_idx,
+                          float *best_dist, int32_t *flags, void *scratch, hipStream_t s) {
   const int tr = tile_rows;
   const int tiles_m = (int)((M + tr - 1) / tr);
   const int vec = (P % 4 == 0) && al16(S32) && al16(D32);
+  char *w = static_cast<char *>(scratch);
+  float *stats = reinterpret_cast<float *>(w);
+  unsigned *count = reinterpret_cast<unsigned *>(w + 16);
+  int32_t *list = reinterpret_cast<int32_t *>(w + 256);
+  auto *keys = reinterpret_cast<unsigned long long *>(w + 256 + (((size_t)N * 4 + 255) & ~(size_t)255));
+  CertBounds cb;
+  cb.g_acc = (float)gamma_of((double)P + 64.0, 0x1p-23);
+  cb.g_run = (float)gamma_of((double)(P / 64) + 16.0, 0x1p-24);
+  hipError_t e = launch_fill_zero(count, 4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(chunk_stats_kernel, dim3(1), dim3(1024), 0, s, sn, se, M, stats);
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, cand, tiles_m,
-                     tr, N, P, (uint32_t)m_offset, S32, D32, sn, dn, best_idx, best_dist, vec);
-  return hipGetLastError();
-}
-
-// hi = bf16(x) (round to nearest even), lo = bf16(x - hi): hi + lo carries
-// x to about 16 significant bits.
-__global__ __launch_bounds__(256) void split_bf16_kernel(const float *__restrict__ x, int64_t n,
-                                                         uint16_t *__restrict__ out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float v = x[i];
-    const uint16_t h = f32_to_bf16(v);
-    out[i] = h;
-    out[n + i] = f32_to_bf16(v - bf16_to_f32(h));
-  }
-}
-
-hipError_t launch_split_bf16(const float *x, int64_t n, uint16_t *out, hipStream_t s) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, out);
+                     tr, M, N, P, (uint32_t)m_offset, S32, D32, sn, dn, se, de, stats, cb, best_idx,
+                     best_dist, flags, count, list, keys, vec);
+  hipLaunchKernelGGL(fallback_kernel, dim3(1024), dim3(256), 0, s, S32, D32, M, P,
+                     (uint32_t)m_offset, count, list, keys, vec);
+  hipLaunchKernelGGL(fallback_unpack_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                     count, list, keys, best_idx, best_dist);
   return hipGetLastError();
 }
 

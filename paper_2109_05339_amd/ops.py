@@ -17,7 +17,7 @@ from ._lib import check
 
 REAL, COMPLEX = 0, 1
 F32, BF16 = 0, 1
-MATCH_FP32, MATCH_BF16_RESCORE8, MATCH_BF16X3_RESCORE8 = 0, 1, 2
+MATCH_FP32, MATCH_BF16_RESCORE8 = 0, 1
 MERGE_ACCUMULATE, MERGE_DEFER = 1, 2
 
 
@@ -112,22 +112,21 @@ class Plan:
         _need(model, "model", self.cdtype, self.device, (N, N, N))
         check(_lib.lib().spfel_set_model(self._h, _p(model), _stream(self.device)))
 
-    def slice(self, quats: torch.Tensor, det_q: Optional[torch.Tensor] = None, out: bool = True,
-              bf16: bool = False, norms: bool = False):
+    def slice(self, quats: torch.Tensor, det_q: Optional[torch.Tensor] = None,
+              norms: bool = False):
         """Model images at orientations ``quats`` (M,4) and detector points
-        ``det_q`` (P,3) (None: the registered detector).  Returns (slices or
-        None, bf16 copy or None, squared norms or None)."""
+        ``det_q`` (P,3) (None: the registered detector).  Returns (slices,
+        squared norms or None)."""
         _need(quats, "quats", torch.float32, self.device)
         if quats.dim() != 2 or quats.shape[1] != 4:
             raise ValueError("quats must be (M, 4)")
         det_q, P = self._detector(det_q)
         M = quats.shape[0]
-        s = torch.empty((M, P), dtype=self.cdtype, device=self.device) if out else None
-        sb = torch.empty((M, P), dtype=torch.bfloat16, device=self.device) if bf16 else None
+        s = torch.empty((M, P), dtype=self.cdtype, device=self.device)
         sn = torch.empty((M,), dtype=torch.float32, device=self.device) if norms else None
-        check(_lib.lib().spfel_slice(self._h, _p(quats), M, _p(det_q), P, _p(s), _p(sb), _p(sn),
+        check(_lib.lib().spfel_slice(self._h, _p(quats), M, _p(det_q), P, _p(s), _p(sn),
                                      _stream(self.device)))
-        return s, sb, sn
+        return s, sn
 
     def merge_adjoint(self, quats: torch.Tensor, det_q: Optional[torch.Tensor],
                       values: torch.Tensor, weights: Optional[torch.Tensor] = None,
@@ -150,27 +149,33 @@ class Plan:
                                              _p(weights), _p(out), flags, _stream(self.device)))
         return out
 
-    def orient(self, quats: torch.Tensor, images: torch.Tensor, image_norm2: torch.Tensor,
-               best_idx: torch.Tensor, best_dist: torch.Tensor, mode: int = 0,
-               chunk: int = 2048, images_f32: Optional[torch.Tensor] = None,
-               det_q: Optional[torch.Tensor] = None, overlap: bool = True) -> tuple:
-        """Slice ``quats`` in chunks and match ``images`` against each chunk,
-        the slicing of one chunk overlapping the matching of the previous
-        on a second stream; folds into (best_idx, best_dist) in place."""
+    def orient(self, quats: torch.Tensor, images, best_idx: torch.Tensor,
+               best_dist: torch.Tensor, mode: int = MATCH_FP32, chunk: int = 2048,
+               det_q: Optional[torch.Tensor] = None, overlap: bool = True,
+               flags: Optional[torch.Tensor] = None) -> tuple:
+        """Slice ``quats`` in chunks and match the images against each chunk
+        (the slicing of one chunk may overlap the matching of the previous on
+        a second stream); folds into (best_idx, best_dist) in place.
+        ``images``: ``ImagesF32`` (FP32 mode) or ``ImagesBF16`` (BF16 mode)."""
         if self.domain != REAL:
             raise ValueError("orient needs a REAL plan")
         _need(quats, "quats", torch.float32, self.device)
         det_q, P = self._detector(det_q)
-        dt = torch.float32 if mode == MATCH_FP32 else torch.bfloat16
-        _need(images, "images", dt, self.device)
-        n_img = images.shape[-2]
-        if images.shape[-1] != P:
+        if mode == MATCH_FP32:
+            if not isinstance(images, ImagesF32):
+                raise TypeError("FP32 mode takes ImagesF32")
+            ops_img, n2, f32, err, centre = images.x, images.norm2, None, None, None
+        else:
+            if not isinstance(images, ImagesBF16):
+                raise TypeError("BF16 mode takes ImagesBF16")
+            ops_img, n2, f32, err, centre = images.b16, images.norm2, images.x, images.err, images.centre
+        n_img = ops_img.shape[0]
+        if ops_img.shape[1] != P:
             raise ValueError("images and detector disagree on P")
-        _need(image_norm2, "image_norm2", torch.float32, self.device, (n_img,))
         _need(best_idx, "best_idx", torch.int32, self.device, (n_img,))
         _need(best_dist, "best_dist", torch.float32, self.device, (n_img,))
-        if mode != MATCH_FP32:
-            _need(images_f32, "images_f32", torch.float32, self.device, (n_img, P))
+        if flags is not None:
+            _need(flags, "flags", torch.int32, self.device, (n_img,))
         M = quats.shape[0]
         c = max(1, min(chunk, M))
         need = int(_lib.lib().spfel_orient_workspace_bytes(c, n_img, P, mode))
@@ -187,9 +192,9 @@ class Plan:
             ws = torch.empty((need,), dtype=torch.uint8, device=self.device)
             self._orient_ws = ws
         ws.record_stream(aux)
-        check(_lib.lib().spfel_orient(self._h, _p(quats), M, _p(det_q), P, _p(images),
-                                      _p(image_norm2), _p(images_f32), n_img, mode, c,
-                                      _p(best_idx), _p(best_dist), _p(ws), ws.numel(),
+        check(_lib.lib().spfel_orient(self._h, _p(quats), M, _p(det_q), P, _p(ops_img), _p(n2),
+                                      _p(f32), _p(err), _p(centre), n_img, mode, c,
+                                      _p(best_idx), _p(best_dist), _p(flags), _p(ws), ws.numel(),
                                       main.cuda_stream, aux.cuda_stream))
         return best_idx, best_dist
 
@@ -226,13 +231,51 @@ def row_norm2(x: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def split_bf16(x: torch.Tensor) -> torch.Tensor:
-    """(2, *x.shape) bfloat16 planes hi = bf16(x), lo = bf16(x - hi) of a
-    float32 tensor (for MATCH_BF16X3_RESCORE8)."""
+def column_mean(x: torch.Tensor, round_to_integer: bool = True) -> torch.Tensor:
+    """Per-column mean of a (rows, cols) float32 matrix (rounded to integers
+    by default): the centre of the BF16 matcher's operands."""
     _need(x, "x", torch.float32, x.device)
-    out = torch.empty((2,) + tuple(x.shape), dtype=torch.bfloat16, device=x.device)
-    check(_lib.lib().spfel_split_bf16(_p(x), x.numel(), _p(out), _stream(x.device)))
+    if x.dim() != 2 or x.shape[0] < 1:
+        raise ValueError("column_mean takes a matrix with at least one row")
+    out = torch.empty((x.shape[1],), dtype=torch.float32, device=x.device)
+    check(_lib.lib().spfel_column_mean(_p(x), x.shape[0], x.shape[1], int(bool(round_to_integer)),
+                                       _p(out), _stream(x.device)))
     return out
+
+
+def bf16_centred(x: torch.Tensor, centre: Optional[torch.Tensor] = None) -> tuple:
+    """(bf16(x - centre), squared norms of those BF16 rows, upper bounds on
+    their rounding-error norms) of a (rows, cols) float32 matrix."""
+    _need(x, "x", torch.float32, x.device)
+    if x.dim() != 2:
+        raise ValueError("bf16_centred takes a matrix")
+    if centre is not None:
+        _need(centre, "centre", torch.float32, x.device, (x.shape[1],))
+    out = torch.empty(tuple(x.shape), dtype=torch.bfloat16, device=x.device)
+    n2 = torch.empty((x.shape[0],), dtype=torch.float32, device=x.device)
+    err = torch.empty((x.shape[0],), dtype=torch.float32, device=x.device)
+    check(_lib.lib().spfel_bf16_centred(_p(x), x.shape[0], x.shape[1], _p(centre), _p(out), _p(n2),
+                                        _p(err), _stream(x.device)))
+    return out, n2, err
+
+
+class ImagesF32:
+    """Float32 matcher operand: rows and their squared norms."""
+
+    def __init__(self, x: torch.Tensor):
+        self.x = x
+        self.norm2 = row_norm2(x)
+
+
+class ImagesBF16:
+    """BF16 matcher operand: the float32 rows, a centre (rounded column mean
+    of these rows unless given), and the centred BF16 rows with their norms
+    and rounding-error bounds."""
+
+    def __init__(self, x: torch.Tensor, centre: Optional[torch.Tensor] = None):
+        self.x = x
+        self.centre = column_mean(x) if centre is None else centre
+        self.b16, self.norm2, self.err = bf16_centred(x, self.centre)
 
 
 def match_workspace_bytes(M: int, n_img: int, P: int, mode: int = MATCH_FP32) -> int:
@@ -245,31 +288,26 @@ def new_best(n_img: int, device) -> tuple:
             torch.full((n_img,), float("inf"), dtype=torch.float32, device=device))
 
 
-def match_sizes(slices_shape: tuple, images_shape: tuple, mode: int) -> tuple:
-    """(M, n_img, P) of matcher operands: (M, P) and (n_img, P), or for
-    MATCH_BF16X3_RESCORE8 the (2, M, P) and (2, n_img, P) hi/lo planes."""
-    ndim = 3 if mode == MATCH_BF16X3_RESCORE8 else 2
-    ok = (len(slices_shape) == ndim and len(images_shape) == ndim
-          and slices_shape[-1] == images_shape[-1]
-          and (ndim == 2 or (slices_shape[0] == 2 and images_shape[0] == 2)))
-    if not ok:
-        raise ValueError(f"matcher operands {slices_shape} and {images_shape} do not fit mode {mode}: "
-                         "(M, P) and (n_img, P), or (2, M, P) and (2, n_img, P) planes for BF16X3")
-    return slices_shape[-2], images_shape[-2], slices_shape[-1]
-
-
 def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
           image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
           m_offset: int = 0, mode: int = MATCH_FP32, slices_f32: Optional[torch.Tensor] = None,
-          images_f32: Optional[torch.Tensor] = None,
+          images_f32: Optional[torch.Tensor] = None, slice_err: Optional[torch.Tensor] = None,
+          image_err: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None,
           workspace: Optional[torch.Tensor] = None) -> tuple:
     """Fold the nearest model image of each image into (best_idx, best_dist)
-    in place and return them."""
+    in place and return them.  FP32 mode: float32 (M, P) / (n_img, P) rows
+    and their norms.  BF16 mode: the outputs of ``bf16_centred`` for both
+    sides (one centre), plus the float32 rows and optional per-image
+    ``flags`` (int32, |= 1 where the FP32 fallback ran)."""
     dt = torch.float32 if mode == MATCH_FP32 else torch.bfloat16
     dev = slices.device
     _need(slices, "slices", dt, dev)
     _need(images, "images", dt, dev)
-    M, n_img, P = match_sizes(tuple(slices.shape), tuple(images.shape), mode)
+    if slices.dim() != 2 or images.dim() != 2 or slices.shape[1] != images.shape[1]:
+        raise ValueError(f"matcher operands {tuple(slices.shape)} and {tuple(images.shape)}: "
+                         "expected (M, P) and (n_img, P)")
+    M, P = slices.shape
+    n_img = images.shape[0]
     _need(slice_norm2, "slice_norm2", torch.float32, dev, (M,))
     _need(image_norm2, "image_norm2", torch.float32, dev, (n_img,))
     _need(best_idx, "best_idx", torch.int32, dev, (n_img,))
@@ -277,11 +315,26 @@ def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
     if mode != MATCH_FP32:
         _need(slices_f32, "slices_f32", torch.float32, dev, (M, P))
         _need(images_f32, "images_f32", torch.float32, dev, (n_img, P))
+        _need(slice_err, "slice_err", torch.float32, dev, (M,))
+        _need(image_err, "image_err", torch.float32, dev, (n_img,))
+        if flags is not None:
+            _need(flags, "flags", torch.int32, dev, (n_img,))
     need = match_workspace_bytes(M, n_img, P, mode)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty((need,), dtype=torch.uint8, device=dev)
     check(_lib.lib().spfel_match(_p(slices), _p(slice_norm2), _p(images), _p(image_norm2), M,
                                  n_img, P, m_offset, mode, _p(slices_f32), _p(images_f32),
-                                 _p(best_idx), _p(best_dist), _p(workspace), workspace.numel(),
-                                 _stream(dev)))
+                                 _p(slice_err), _p(image_err), _p(best_idx), _p(best_dist),
+                                 _p(flags), _p(workspace), workspace.numel(), _stream(dev)))
     return best_idx, best_dist
+
+
+def match_bf16(slices_f32: torch.Tensor, images: "ImagesBF16", best_idx: torch.Tensor,
+               best_dist: torch.Tensor, m_offset: int = 0, flags: Optional[torch.Tensor] = None,
+               workspace: Optional[torch.Tensor] = None) -> tuple:
+    """BF16 matching of float32 model images against prepared images:
+    centres the model images with the images' centre, then ``match``."""
+    sb, sn, se = bf16_centred(slices_f32, images.centre)
+    return match(sb, sn, images.b16, images.norm2, best_idx, best_dist, m_offset=m_offset,
+                 mode=MATCH_BF16_RESCORE8, slices_f32=slices_f32, images_f32=images.x,
+                 slice_err=se, image_err=images.err, flags=flags, workspace=workspace)

@@ -77,22 +77,38 @@ def test_match_validation_before_launch():
     L = spfel.lib()
     p = ctypes.c_void_p(4096)
     args = dict(slices=p, sn=p, images=p, dn=p, M=10, N=10, P=64, off=0, mode=0, s32=None,
-                d32=None, idx=p, dist=p, ws=p, wsb=1 << 20, st=None)
+                d32=None, se=None, de=None, idx=p, dist=p, flags=None, ws=p, wsb=1 << 20, st=None)
 
     def call(**kw):
         a = dict(args)
         a.update(kw)
         return L.spfel_match(a["slices"], a["sn"], a["images"], a["dn"], a["M"], a["N"], a["P"],
-                             a["off"], a["mode"], a["s32"], a["d32"], a["idx"], a["dist"], a["ws"],
-                             a["wsb"], a["st"])
+                             a["off"], a["mode"], a["s32"], a["d32"], a["se"], a["de"], a["idx"],
+                             a["dist"], a["flags"], a["ws"], a["wsb"], a["st"])
     assert call(M=-1) == _lib.EINVAL
     assert call(mode=5) == _lib.EINVAL
+    assert call(mode=2) == _lib.EINVAL                        # no split-BF16 mode
     assert call(off=2 ** 31 - 5) == _lib.ERANGE
     assert call(slices=None) == _lib.EINVAL
     assert call(mode=1) == _lib.EINVAL                        # no float32 data to rescore
+    assert call(mode=1, s32=p, d32=p) == _lib.EINVAL          # no rounding-error norms
     assert call(wsb=8) == _lib.EINVAL                         # workspace too small
+    assert call(ws=ctypes.c_void_p(4096 + 16)) == _lib.EINVAL  # workspace not 256-byte aligned
     assert call(slices=ctypes.c_void_p(4098)) == _lib.EINVAL  # misaligned
     assert call(M=0) == _lib.OK and call(N=0) == _lib.OK      # empty: nothing to do
+
+
+def test_operand_call_validation():
+    L = spfel.lib()
+    p = ctypes.c_void_p(4096)
+    assert L.spfel_column_mean(p, 0, 8, 1, p, None) == _lib.EINVAL      # no rows
+    assert L.spfel_column_mean(None, 3, 8, 1, p, None) == _lib.EINVAL
+    assert L.spfel_column_mean(p, 3, 0, 1, p, None) == _lib.OK
+    assert L.spfel_column_mean(ctypes.c_void_p(4098), 3, 8, 1, p, None) == _lib.EINVAL
+    assert L.spfel_bf16_centred(p, -1, 8, None, p, p, p, None) == _lib.EINVAL
+    assert L.spfel_bf16_centred(p, 0, 8, None, p, p, p, None) == _lib.OK
+    assert L.spfel_bf16_centred(p, 3, 8, None, None, p, p, None) == _lib.EINVAL   # out NULL
+    assert L.spfel_bf16_centred(p, 3, 8, ctypes.c_void_p(4097), p, p, p, None) == _lib.EINVAL
 
 
 def test_workspace_sizes():
@@ -102,7 +118,9 @@ def test_workspace_sizes():
     assert ws(10000, 2048, 16384, spfel.MATCH_FP32) == 2048 * 8          # 2.5 rounds: no split-K
     # 8 x 16 tiles are a quarter of a round of resident blocks: split K in four
     assert ws(1000, 2048, 16384, spfel.MATCH_FP32) == 2048 * 8 + 512 + 128 * 4 * 128 * 128 * 4
-    assert ws(1000, 256, 4096, spfel.MATCH_BF16_RESCORE8) == 8 * 256 * 8 * 4   # 8 m-tiles of 128
+    # 8 m-tiles of 128 x 8 candidates, then chunk maxima + count (256 B), the
+    # fallback list (256-byte rounded) and its keys
+    assert ws(1000, 256, 4096, spfel.MATCH_BF16_RESCORE8) == 8 * 256 * 8 * 4 + 256 + 1024 + 256 * 8
     assert ws(0, 0, 0, spfel.MATCH_FP32) == 256
 
 
@@ -117,16 +135,3 @@ def test_row_norm2_validation():
 def test_exceptions_map_codes():
     with pytest.raises(spfel.SpfelInvalidArgument):
         _lib.check(spfel.lib().spfel_row_norm2(None, 7, 1, 1, None, None))
-
-
-def test_match_operand_shapes():
-    from paper_2109_05339_amd.ops import match_sizes
-    assert match_sizes((1000, 4096), (256, 4096), spfel.MATCH_FP32) == (1000, 256, 4096)
-    assert match_sizes((1000, 4096), (256, 4096), spfel.MATCH_BF16_RESCORE8) == (1000, 256, 4096)
-    assert match_sizes((2, 1000, 4096), (2, 256, 4096), spfel.MATCH_BF16X3_RESCORE8) == (1000, 256, 4096)
-    for bad in [((1000, 4096), (256, 4095), spfel.MATCH_FP32),
-                ((2, 1000, 4096), (2, 256, 4096), spfel.MATCH_FP32),
-                ((1000, 4096), (256, 4096), spfel.MATCH_BF16X3_RESCORE8),
-                ((3, 1000, 4096), (2, 256, 4096), spfel.MATCH_BF16X3_RESCORE8)]:
-        with pytest.raises(ValueError):
-            match_sizes(*bad)

@@ -20,10 +20,6 @@ def chain_fp32(P):      # the FP32 matcher's documented accumulation chain
     return 36 + -(-P // 32)
 
 
-def chain_rescore(P):
-    return 10 + -(-P // 64)
-
-
 @functools.lru_cache(maxsize=None)
 def c1_data(n_refs=1000, n_img=300):
     """C1-shaped matcher inputs: the molecule's intensity at the reference
@@ -120,70 +116,134 @@ def test_running_best_is_respected():
     assert np.all(bi[:10] < 1000)
 
 
+def chain_direct(P):    # rescore and fallback: direct sums of (s - d)^2
+    return P // 64 + 16
+
+
 def run_bf16(S, D, chunks=None):
+    """BF16 matcher with the oracle's centre (rounded image mean)."""
     St, Dt = gpu(S), gpu(D)
-    Sb, Db = St.to(torch.bfloat16), Dt.to(torch.bfloat16)
-    sn, dn = spfel.row_norm2(St), spfel.row_norm2(Dt)
+    im = spfel.ImagesBF16(Dt, centre=gpu(om.centre_rounded_mean(D)))
     bi, bd = spfel.new_best(D.shape[0], DEV)
+    fl = torch.zeros(D.shape[0], dtype=torch.int32, device=DEV)
     if chunks is None:
         chunks = [(0, S.shape[0])]
     for a, b in chunks:
-        spfel.match(Sb[a:b], sn[a:b], Db, dn, bi, bd, m_offset=a, mode=spfel.MATCH_BF16_RESCORE8,
-                    slices_f32=St[a:b], images_f32=Dt)
-    return host(bi), host(bd)
+        spfel.match_bf16(St[a:b].contiguous(), im, bi, bd, m_offset=a, flags=fl)
+    return host(bi), host(bd), host(fl)
+
+
+def decided_by(ex, E):
+    """Images whose exact top-2 gap exceeds the two distances' bounds E."""
+    cols = np.arange(ex.shape[1])
+    order = np.argsort(ex, axis=0, kind="stable")
+    m1, m2 = order[0], order[1]
+    return ex[m2, cols] - ex[m1, cols] > E[m1, cols] + E[m2, cols]
+
+
+def check_bf16(S, D, ib, db, fl, min_cert):
+    """The BF16 path against the oracle: exact argmin wherever the exact gap
+    exceeds the float32 direct-sum bound (a superset of the FP32 matcher's
+    decided images), distances within that bound, and every image the GPU
+    certified is certified by the oracle's exact-arithmetic certificate."""
+    P = S.shape[1]
+    ex = om.distances_expanded(S.astype(np.float64), D.astype(np.float64))
+    am = om.argmin_first(ex)
+    cols = np.arange(D.shape[0])
+    g = om.gamma(chain_direct(P))
+    dec_direct = decided_by(ex, 2 * g * ex)
+    assert np.all(ib[dec_direct] == am[dec_direct])
+    assert np.all(np.abs(db - ex[ib, cols]) <= 2 * g * ex[ib, cols] + 1e-30)
+    # any returned index is a near-minimiser within the direct-sum bounds
+    assert np.all(ex[ib, cols] - ex[am, cols] <= 2 * g * (ex[ib, cols] + ex[am, cols]))
+    c = om.centre_rounded_mean(D)
+    Sv, _, e = om.bf16_centred(S, c)
+    Dv, _, f = om.bf16_centred(D, c)
+    b = om.centred_proxy(Sv, Dv)
+    cert_oracle = om.centred_certificate(b, e, f, ex, 8)
+    cert_gpu = fl == 0
+    assert np.all(cert_oracle[cert_gpu])
+    assert cert_gpu.mean() >= min_cert
+    top8 = om.topk(b, 8)
+    in8 = np.array([am[n] in top8[:, n] for n in cols])
+    return dec_direct, cert_gpu, in8
 
 
 def test_bf16_rescore_matches_fp32_argmin_on_decided_images():
     S, D = c1_data()
     i32, d32, _, _ = run_fp32(S, D)
-    ib, db = run_bf16(S, D)
+    ib, db, fl = run_bf16(S, D)
+    dec_direct, cert, in8 = check_bf16(S, D, ib, db, fl, min_cert=0.99)
     ex, E = exact_and_bounds(S, D, chain_fp32(S.shape[1]))
-    cols = np.arange(D.shape[0])
-    order = np.argsort(ex, axis=0, kind="stable")
-    m1, m2 = order[0], order[1]
-    gap = ex[m2, cols] - ex[m1, cols]
-    decided = gap > E[m1, cols] + E[m2, cols]
-    # certificate of the top-8 from the BF16 proxy bound (images are exact
-    # small integers, so only the slices' rounding counts)
-    S64, D64 = S.astype(np.float64), D.astype(np.float64)
-    absdot = np.abs(S64) @ np.abs(D64).T
-    b = (S64 ** 2).sum(1)[:, None] + (D64 ** 2).sum(1)[None, :] - 2 * (om.bf16_round(S).astype(np.float64) @ D64.T)
-    ebf = om.bf16_proxy_bound(absdot, om.fp32_distance_bound((S64 ** 2).sum(1)[:, None], (D64 ** 2).sum(1)[None, :], absdot, S.shape[1] + 2), exact_images=True)
-    cert = om.topk_certified(b, ebf, 8)
-    # images whose exact argmin is in the true proxy top-8 and decided must agree
-    top8 = om.topk(b, 8)
-    in8 = np.array([m1[n] in top8[:, n] for n in cols])
-    ok = decided & in8
-    assert np.all(ib[ok] == i32[ok])
-    assert np.all(ib[cert & decided] == i32[cert & decided])
-    assert ok.mean() >= 0.8
-    # the rescored distance is an exact float32 evaluation
-    Lr = chain_rescore(S.shape[1])
-    Eres = om.fp32_distance_bound((S64 ** 2).sum(1)[ib], (D64 ** 2).sum(1), absdot[ib, cols], Lr)
-    assert np.all(np.abs(db - ex[ib, cols]) <= Eres + E[ib, cols])
-    print(f"bf16: decided {decided.mean():.3f}, certified {cert.mean():.3f}, in-top8 {in8.mean():.4f}, "
-          f"agree {np.mean(ib == i32):.4f}")
+    dec32 = decided_by(ex, E)
+    am = om.argmin_first(ex)
+    # the FP32 matcher's decided images: both paths give the exact argmin
+    assert np.all(ib[dec32] == am[dec32]) and np.all(i32[dec32] == am[dec32])
+    assert dec_direct.mean() >= 0.95 and in8.mean() >= 0.99
+    print(f"bf16: decided (fp32 bound) {dec32.mean():.3f}, decided (direct bound) "
+          f"{dec_direct.mean():.3f}, certified {cert.mean():.4f}, in proxy top-8 {in8.mean():.4f}, "
+          f"agree with fp32 {np.mean(ib == i32):.4f}")
 
 
 def test_bf16_chunked_streaming():
-    """Streaming chunks rescore each chunk's own top-8 (a superset of the
-    one-shot candidates), so both agree with the exact argmin wherever the
-    exact minimiser is decided and inside the one-shot proxy top-8."""
+    """Chunks streamed into the running best give the exact argmin on the
+    same images as one launch."""
     S, D = c1_data()
     a = run_bf16(S, D)
-    b = run_bf16(S, D, chunks=[(0, 500), (500, 1000)])
-    ex, E = exact_and_bounds(S, D, chain_fp32(S.shape[1]))
-    cols = np.arange(D.shape[0])
-    order = np.argsort(ex, axis=0, kind="stable")
-    m1, m2 = order[0], order[1]
-    decided = (ex[m2, cols] - ex[m1, cols]) > E[m1, cols] + E[m2, cols]
-    S64, D64 = S.astype(np.float64), D.astype(np.float64)
-    b16 = (S64 ** 2).sum(1)[:, None] + (D64 ** 2).sum(1)[None, :] - 2 * (om.bf16_round(S).astype(np.float64) @ D64.T)
-    top8 = om.topk(b16, 8)
-    ok = decided & np.array([m1[n] in top8[:, n] for n in cols])
-    assert np.all(a[0][ok] == m1[ok]) and np.all(b[0][ok] == m1[ok])
-    # chunked never does worse than one-shot in exact distance
-    assert np.all(ex[b[0], cols] <= ex[a[0], cols] + E[b[0], cols] + E[a[0], cols])
+    b = run_bf16(S, D, chunks=[(0, 500), (500, 501), (501, 1000)])
+    check_bf16(S, D, *a, min_cert=0.99)
+    dec, _, _ = check_bf16(S, D, *b, min_cert=0.99)
+    np.testing.assert_array_equal(a[0][dec], b[0][dec])
+
+
+def test_bf16_uncertified_images_fall_back_to_fp32():
+    """Twelve model images that differ only below BF16 resolution: the proxy
+    cannot rank them, so images matching them are not certified and the
+    float32 fallback over all model images finds the exact minimiser."""
+    g = np.random.default_rng(5)
+    P = 1024
+    base = g.gamma(2.0, 100.0, P)
+    S = np.concatenate([np.stack([base * (1 + 3e-4 * g.standard_normal(P)) for _ in range(12)]),
+                        g.gamma(2.0, 100.0, (300, P))]).astype(np.float32)
+    D = np.concatenate([S[[3, 7, 11]] + g.normal(0, 0.05, (3, P)),
+                        g.poisson(S[[20, 100, 250, 311]])]).astype(np.float32)
+    ib, db, fl = run_bf16(S, D, chunks=[(0, 150), (150, 312)])
+    ex = om.distances_direct(S, D)
+    np.testing.assert_array_equal(ib, om.argmin_first(ex))
+    assert np.all(fl[:3] == 1) and np.all(fl[3:] == 0)
+    assert np.all(np.abs(db - ex[ib, np.arange(7)]) <= 2 * om.gamma(chain_direct(P)) * ex[ib, np.arange(7)])
+
+
+def test_column_mean_against_oracle():
+    g = np.random.default_rng(6)
+    D = g.poisson(g.gamma(2.0, 20.0, (700, 1037))).astype(np.float32)
+    m = host(spfel.column_mean(gpu(D), round_to_integer=False))
+    ref = D.astype(np.float64).mean(0)
+    L = 700 // 32 + 32 + 2
+    assert np.all(np.abs(m - ref) <= om.gamma(L) * ref + 1e-30)
+    r = host(spfel.column_mean(gpu(D)))
+    near_half = np.abs(ref - np.floor(ref) - 0.5) < 1e-3
+    np.testing.assert_array_equal(r[~near_half], np.round(ref)[~near_half])
+
+
+@pytest.mark.parametrize("rows,cols,aligned", [(37, 4096, True), (5, 1001, True), (9, 256, False)])
+def test_bf16_centred_against_oracle(rows, cols, aligned):
+    g = np.random.default_rng(cols)
+    X = (g.gamma(1.5, 40.0, (rows, cols)) * g.uniform(0.5, 2.0, (rows, 1))).astype(np.float32)
+    c = np.round(X.mean(0)).astype(np.float32)
+    Xt = gpu(X)
+    if not aligned:    # rows one element into a larger buffer
+        buf = torch.empty(rows * cols + 4, dtype=torch.float32, device=DEV)
+        Xt = buf[1:1 + rows * cols].view(rows, cols)
+        Xt.copy_(gpu(X))
+    out, n2, err = spfel.bf16_centred(Xt, gpu(c))
+    v, rn2, rerr = om.bf16_centred(X, c)
+    got = host(out.float()).astype(np.float64)
+    np.testing.assert_array_equal(got, v)
+    L = cols // 256 + 16
+    assert np.all(np.abs(host(n2) - rn2) <= om.gamma(L) * rn2)
+    e = host(err).astype(np.float64)
+    assert np.all(e >= rerr) and np.all(e <= rerr * (1 + 4 * om.gamma(L)) + 2 ** -22 * np.sqrt(rn2))
 
 
 @pytest.mark.parametrize("M,N,P,misalign", [
@@ -196,38 +256,36 @@ def test_bf16_large_shapes_against_oracle_on_sampled_images(M, N, P, misalign):
     """Shapes that fill >= 4 rounds of 256 x 256 tiles: the large-tile BF16
     kernel when P is a whole number of its K steps and the operands are
     16-byte aligned, else the 128-row kernel.  The oracle checks 192 sampled
-    images exactly."""
+    images: exact argmin wherever the direct-sum bound decides."""
     g = np.random.default_rng(11)
     base = g.gamma(2.0, 10.0, (M, P)).astype(np.float32)
     pick = g.integers(0, M, N)
     D = g.poisson(base[pick]).astype(np.float32)
-    assert spfel.match_workspace_bytes(M, N, P, spfel.MATCH_BF16_RESCORE8) == -(-M // 128) * N * 32
     St, Dt = gpu(base), gpu(D)
+    c = gpu(om.centre_rounded_mean(D))
+    im = spfel.ImagesBF16(Dt, centre=c)
+    sb, sn, se = spfel.bf16_centred(St, c)
     if misalign:   # views one element into a larger buffer
-        Sb = torch.empty(M * P + 8, dtype=torch.bfloat16, device=DEV)[1:1 + M * P].view(M, P)
-        Sb.copy_(St)
-    else:
-        Sb = St.to(torch.bfloat16)
-    Db = Dt.to(torch.bfloat16)
+        buf = torch.empty(M * P + 8, dtype=torch.bfloat16, device=DEV)
+        sbm = buf[1:1 + M * P].view(M, P)
+        sbm.copy_(sb)
+        sb = sbm
     bi, bd = spfel.new_best(N, DEV)
-    spfel.match(Sb, spfel.row_norm2(St), Db, spfel.row_norm2(Dt), bi, bd,
-                mode=spfel.MATCH_BF16_RESCORE8, slices_f32=St, images_f32=Dt)
-    ib, db = host(bi), host(bd)
+    fl = torch.zeros(N, dtype=torch.int32, device=DEV)
+    spfel.match(sb, sn, im.b16, im.norm2, bi, bd, mode=spfel.MATCH_BF16_RESCORE8, slices_f32=St,
+                images_f32=Dt, slice_err=se, image_err=im.err, flags=fl)
+    ib, db, fl = host(bi), host(bd), host(fl)
     cols = np.sort(g.choice(N, 192, replace=False))
     S64, Ds = base.astype(np.float64), D[cols].astype(np.float64)
     ex = om.distances_expanded(S64, Ds)
-    absdot = np.abs(S64) @ np.abs(Ds).T
-    E = om.fp32_distance_bound((S64 ** 2).sum(1)[:, None], (Ds ** 2).sum(1)[None, :], absdot, chain_fp32(P))
-    order = np.argsort(ex, axis=0, kind="stable")
-    c = np.arange(len(cols))
-    m1, m2 = order[0], order[1]
-    decided = ex[m2, c] - ex[m1, c] > E[m1, c] + E[m2, c]
-    b16 = (S64 ** 2).sum(1)[:, None] + (Ds ** 2).sum(1)[None, :] - 2 * (om.bf16_round(base).astype(np.float64) @ Ds.T)
-    top8 = om.topk(b16, 8)
-    ok = decided & np.array([m1[n] in top8[:, n] for n in c])
-    assert ok.mean() >= 0.9
-    np.testing.assert_array_equal(ib[cols][ok], m1[ok])
-    assert np.all(np.abs(db[cols] - ex[ib[cols], c]) <= 2 * E[ib[cols], c])
+    c_ = np.arange(len(cols))
+    am = om.argmin_first(ex)
+    gd = om.gamma(chain_direct(P))
+    dec = decided_by(ex, 2 * gd * ex)
+    assert dec.mean() >= 0.9
+    np.testing.assert_array_equal(ib[cols][dec], am[dec])
+    assert np.all(np.abs(db[cols] - ex[ib[cols], c_]) <= 2 * gd * ex[ib[cols], c_])
+    assert np.mean(fl == 0) >= 0.99
 
 
 @pytest.mark.parametrize("mode,M,N,P", [
@@ -243,16 +301,18 @@ def test_full_size_launches_against_oracle_on_sampled_images(mode, M, N, P):
     St = torch.rand((M, P), generator=g, device=DEV) * 40.0
     pick = torch.randint(0, M, (N,), generator=g, device=DEV)
     Dt = torch.poisson(St[pick], generator=g)
-    sn, dn = spfel.row_norm2(St), spfel.row_norm2(Dt)
     bi, bd = spfel.new_best(N, DEV)
+    fl = torch.zeros(N, dtype=torch.int32, device=DEV)
     if mode == spfel.MATCH_FP32:
-        spfel.match(St, sn, Dt, dn, bi, bd)
+        spfel.match(St, spfel.row_norm2(St), Dt, spfel.row_norm2(Dt), bi, bd)
         L = chain_fp32(P)
     else:
-        spfel.match(St.to(torch.bfloat16), sn, Dt.to(torch.bfloat16), dn, bi, bd, mode=mode,
-                    slices_f32=St, images_f32=Dt)
-        L = chain_rescore(P)
+        # centre made with torch, as the inputs are
+        centre = torch.round(Dt.double().mean(0)).float()
+        spfel.match_bf16(St, spfel.ImagesBF16(Dt, centre=centre), bi, bd, flags=fl)
+        L = chain_direct(P)
     ib, db = host(bi), host(bd)
+    assert host(fl).mean() <= 0.01
     cols = np.sort(np.random.default_rng(3).choice(N, 24, replace=False))
     Ds = host(Dt[torch.as_tensor(cols, device=DEV)]).astype(np.float64)
     ex = np.empty((M, len(cols)))

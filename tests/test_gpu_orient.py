@@ -1,5 +1,6 @@
 """The two-stream slice->match pipeline (spfel_orient) gives exactly the
-result of slicing each chunk and matching it into the running best."""
+result of slicing each chunk (centring it, in BF16 mode) and matching it into
+the running best."""
 import functools
 
 import numpy as np
@@ -25,53 +26,58 @@ def inputs():
     return plan, gpu(synth.quaternions(cfg, "ref_quats", 1000)), images
 
 
+def prepared(images, mode):
+    return spfel.ImagesF32(images) if mode == spfel.MATCH_FP32 else spfel.ImagesBF16(images)
+
+
 def reference(plan, q, images, mode, chunk):
-    dn = spfel.row_norm2(images)
+    im = prepared(images, mode)
     bi, bd = spfel.new_best(images.shape[0], DEV)
-    ix = images if mode == spfel.MATCH_FP32 else (
-        images.to(torch.bfloat16) if mode == spfel.MATCH_BF16_RESCORE8 else spfel.split_bf16(images))
+    fl = torch.zeros(images.shape[0], dtype=torch.int32, device=DEV)
     for c0 in range(0, q.shape[0], chunk):
-        S, Sb, sn = plan.slice(q[c0:c0 + chunk], bf16=mode == spfel.MATCH_BF16_RESCORE8, norms=True)
-        sl = S if mode == spfel.MATCH_FP32 else (Sb if mode == spfel.MATCH_BF16_RESCORE8 else spfel.split_bf16(S))
-        spfel.match(sl, sn, ix, dn, bi, bd, m_offset=c0, mode=mode,
-                    slices_f32=None if mode == spfel.MATCH_FP32 else S,
-                    images_f32=None if mode == spfel.MATCH_FP32 else images)
-    return host(bi), host(bd)
+        if mode == spfel.MATCH_FP32:
+            S, sn = plan.slice(q[c0:c0 + chunk], norms=True)
+            spfel.match(S, sn, im.x, im.norm2, bi, bd, m_offset=c0)
+        else:
+            S, _ = plan.slice(q[c0:c0 + chunk])
+            spfel.match_bf16(S, im, bi, bd, m_offset=c0, flags=fl)
+    return host(bi), host(bd), host(fl)
 
 
-@pytest.mark.parametrize("mode", [spfel.MATCH_FP32, spfel.MATCH_BF16_RESCORE8, spfel.MATCH_BF16X3_RESCORE8])
+@pytest.mark.parametrize("mode", [spfel.MATCH_FP32, spfel.MATCH_BF16_RESCORE8])
 @pytest.mark.parametrize("chunk,overlap", [(300, True), (1000, True), (256, False)])
 def test_orient_equals_chunked_slice_and_match(mode, chunk, overlap):
     plan, q, images = inputs()
     ref = reference(plan, q, images, mode, chunk)
-    dn = spfel.row_norm2(images)
-    ix = images if mode == spfel.MATCH_FP32 else (
-        images.to(torch.bfloat16) if mode == spfel.MATCH_BF16_RESCORE8 else spfel.split_bf16(images))
     bi, bd = spfel.new_best(images.shape[0], DEV)
-    plan.orient(q, ix, dn, bi, bd, mode=mode, chunk=chunk,
-                images_f32=None if mode == spfel.MATCH_FP32 else images, overlap=overlap)
+    fl = torch.zeros(images.shape[0], dtype=torch.int32, device=DEV)
+    plan.orient(q, prepared(images, mode), bi, bd, mode=mode, chunk=chunk, overlap=overlap,
+                flags=fl)
     np.testing.assert_array_equal(host(bi), ref[0])
     np.testing.assert_array_equal(host(bd), ref[1])
+    if mode != spfel.MATCH_FP32:
+        np.testing.assert_array_equal(host(fl), ref[2])
 
 
 def test_orient_fp32_equals_one_shot_match():
     plan, q, images = inputs()
-    S, _, sn = plan.slice(q, norms=True)
-    dn = spfel.row_norm2(images)
+    S, sn = plan.slice(q, norms=True)
+    im = spfel.ImagesF32(images)
     b1 = spfel.new_best(images.shape[0], DEV)
-    spfel.match(S, sn, images, dn, *b1)
+    spfel.match(S, sn, im.x, im.norm2, *b1)
     b2 = spfel.new_best(images.shape[0], DEV)
-    plan.orient(q, images, dn, *b2, chunk=128)
+    plan.orient(q, im, *b2, chunk=128)
     np.testing.assert_array_equal(host(b1[0]), host(b2[0]))
     np.testing.assert_array_equal(host(b1[1]), host(b2[1]))
 
 
 def test_orient_validation():
     plan, q, images = inputs()
-    dn = spfel.row_norm2(images)
     bi, bd = spfel.new_best(images.shape[0], DEV)
-    with pytest.raises((TypeError, ValueError)):
-        plan.orient(q, images.to(torch.bfloat16), dn, bi, bd, mode=spfel.MATCH_BF16_RESCORE8)
+    with pytest.raises(TypeError):
+        plan.orient(q, spfel.ImagesF32(images), bi, bd, mode=spfel.MATCH_BF16_RESCORE8)
+    with pytest.raises(TypeError):
+        plan.orient(q, images, bi, bd)
     cplan = spfel.Plan(9, domain=spfel.COMPLEX, device=DEV)
     with pytest.raises(ValueError):
-        cplan.orient(q, images, dn, bi, bd)
+        cplan.orient(q, spfel.ImagesF32(images), bi, bd)

@@ -25,17 +25,14 @@ def test_real_slices_c1_shape():
     q = synth.quaternions(cfg, "ref_quats", cfg.n_refs)
     plan = make_plan(cfg.n_model)
     plan.set_model(gpu(m))
-    s, sb, sn = plan.slice(gpu(q), gpu(det), out=True, bf16=True, norms=True)
+    s, sn = plan.slice(gpu(q), gpu(det), norms=True)
     torch.cuda.synchronize()
-    s, sb, sn = host(s), host(sb.view(torch.int16)).view(np.uint16), host(sn)
+    s, sn = host(s), host(sn)
     rows = np.r_[0:24, cfg.n_refs - 8:cfg.n_refs]        # first, last (ragged tail) rows
     ref = oracle_slices(m, q[rows], det, real=True)
     assert rel(s[rows], ref) <= TOL
     for r in rows:
         assert rel(s[r], ref[list(rows).index(r)]) <= 3 * TOL
-    # bf16 copy is the round-to-nearest-even of the float32 output, bit for bit
-    ref16 = (omatch.bf16_round(s).view(np.uint32) >> 16).astype(np.uint16)
-    np.testing.assert_array_equal(sb, ref16)
     # norms: |s_m|^2 of the float32 output within the float32 sum bound
     exact = (s.astype(np.float64) ** 2).sum(1)
     L = det.shape[0] // 256 + 10
@@ -49,7 +46,7 @@ def test_complex_slices_random_points_and_ragged_detector():
     q = synth.quaternions(synth.config(4), "image_quats", 7)
     plan = make_plan(N, spfel.COMPLEX)
     plan.set_model(gpu(m, torch.complex64))
-    s, _, sn = plan.slice(gpu(q), gpu(det), norms=True)
+    s, sn = plan.slice(gpu(q), gpu(det), norms=True)
     s = host(s)
     ref = oracle_slices(m.astype(np.complex64).astype(np.complex128), q, det, real=False)
     assert rel(s, ref) <= TOL
@@ -121,9 +118,9 @@ def test_empty_and_nonfinite_inputs():
     plan = make_plan(9)
     plan.set_model(gpu(synth.random_model(1, 9)))
     det = gpu(detector(8))
-    s, _, sn = plan.slice(torch.zeros((0, 4), device=DEV), det, norms=True)
+    s, sn = plan.slice(torch.zeros((0, 4), device=DEV), det, norms=True)
     assert s.shape == (0, 64) and sn.shape == (0,)
-    s, _, sn = plan.slice(gpu(synth.quaternions(synth.config(1), "ref_quats", 3)),
+    s, sn = plan.slice(gpu(synth.quaternions(synth.config(1), "ref_quats", 3)),
                           torch.zeros((0, 3), device=DEV), norms=True)
     assert s.shape == (3, 0) and np.all(host(sn) == 0)
     q = synth.quaternions(synth.config(1), "ref_quats", 3)
@@ -148,9 +145,8 @@ def test_state_and_argument_errors():
     with pytest.raises(TypeError):
         plan.slice(q.double(), det)
     cplan = make_plan(9, spfel.COMPLEX)
-    cplan.set_model(gpu(synth.random_model(1, 9, True), torch.complex64))
-    with pytest.raises(spfel.SpfelUnsupported):
-        cplan.slice(q, det, bf16=True)
+    with pytest.raises(TypeError):
+        cplan.set_model(gpu(synth.random_model(1, 9), torch.float32))
     plan.close()
     with pytest.raises(spfel.SpfelStateError):
         plan.slice(q, det)
@@ -169,12 +165,10 @@ def test_registered_detector_tiles_are_bitwise_equal_to_generic_path(domain):
     else:
         plan.set_model(gpu(synth.complex_perturbation(synth.config(4), model(1)), torch.complex64))
     plan.set_detector(gpu(det))
-    a, ab, an = plan.slice(gpu(q), None, bf16=domain == spfel.REAL, norms=True)
-    b, bb, bn = plan.slice(gpu(q), gpu(det), bf16=domain == spfel.REAL, norms=True)
+    a, an = plan.slice(gpu(q), None, norms=True)
+    b, bn = plan.slice(gpu(q), gpu(det), norms=True)
     np.testing.assert_array_equal(host(a), host(b))
     np.testing.assert_array_equal(host(an), host(bn))
-    if domain == spfel.REAL:
-        np.testing.assert_array_equal(host(ab.view(torch.int16)), host(bb.view(torch.int16)))
 
 
 @pytest.mark.parametrize("cid,rows", [(2, 4), (5, 2)])

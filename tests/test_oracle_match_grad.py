@@ -68,32 +68,6 @@ def test_fp32_distance_bound_holds_and_is_not_vacuous():
     assert np.median(bnd / np.abs(exact)) < 0.5
 
 
-def test_bf16_proxy_bound_and_certificate():
-    g = np.random.default_rng(4)
-    P = 1024
-    base = np.abs(g.standard_normal((60, P))) * 30
-    S = base.astype(np.float32)
-    D = g.poisson(base[[5, 17, 40, 41]] + 0.0).astype(np.float32)   # exact in bf16 (<= 256)
-    assert D.max() <= 256
-    exact = match.distances_expanded(S, D)
-    Sb = match.bf16_round(S).astype(np.float64)
-    Db = match.bf16_round(D).astype(np.float64)
-    np.testing.assert_array_equal(Db, D)
-    sn = (S.astype(np.float64) ** 2).sum(1)
-    dn = (D.astype(np.float64) ** 2).sum(1)
-    b = sn[:, None] + dn[None, :] - 2 * (Sb @ Db.T)
-    absdot = np.abs(S.astype(np.float64)) @ np.abs(D.astype(np.float64)).T
-    ebf = match.bf16_proxy_bound(absdot, 0.0, exact_images=True)
-    assert np.all(np.abs(b - exact) <= ebf)
-    cert = match.topk_certified(b, ebf, 8)
-    am = match.argmin_first(exact)
-    top = match.topk(b, 8)
-    for n in range(D.shape[0]):
-        if cert[n]:
-            assert am[n] in top[:, n]
-    assert cert.any()
-
-
 def test_gradient_matches_central_differences():
     """The loss is quadratic in m, so central differences equal the analytic
     gradient up to rounding."""
