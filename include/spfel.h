@@ -188,6 +188,27 @@ int spfel_match(const void *slices, const float *slice_norm2,
                 int32_t *best_idx, float *best_dist, int32_t *flags,
                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* Size of the per-device scratch array spfel_match_noalloc uses. */
+#define SPFEL_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as spfel_match, without the workspace
+ * arguments.  The workspace lives in a 64 MiB array each GPU holds from the
+ * library's first call on it until the process ends; sizes whose
+ * spfel_match_workspace_bytes exceeds SPFEL_NOALLOC_SCRATCH_BYTES are
+ * rejected with SPFEL_ERANGE.  The call allocates nothing.  Every call on
+ * one GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other threads) race; calls queued on one stream do not.  Runs on
+ * the current device. */
+int spfel_match_noalloc(const void *slices, const float *slice_norm2,
+                        const void *images, const float *image_norm2,
+                        int64_t M, int64_t n_img, int64_t P, int64_t m_offset,
+                        int mode, const float *slices_f32,
+                        const float *images_f32, const float *slice_err,
+                        const float *image_err, int32_t *best_idx,
+                        float *best_dist, int32_t *flags, void *stream);
+
 /* Bytes of workspace spfel_orient needs for this chunk length. */
 size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
                                     int mode);

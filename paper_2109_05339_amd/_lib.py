@@ -57,6 +57,8 @@ SIGNATURES = {
     "spfel_match_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
     "spfel_match": (_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _int, _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spfel_match_noalloc": (_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _int, _vp, _vp,
+                                   _vp, _vp, _vp, _vp, _vp, _vp]),
     "spfel_orient_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
     "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _int, _i64,
                             _vp, _vp, _vp, _vp, _sz, _vp, _vp]),

@@ -288,17 +288,8 @@ def new_best(n_img: int, device) -> tuple:
             torch.full((n_img,), float("inf"), dtype=torch.float32, device=device))
 
 
-def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
-          image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
-          m_offset: int = 0, mode: int = MATCH_FP32, slices_f32: Optional[torch.Tensor] = None,
-          images_f32: Optional[torch.Tensor] = None, slice_err: Optional[torch.Tensor] = None,
-          image_err: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None,
-          workspace: Optional[torch.Tensor] = None) -> tuple:
-    """Fold the nearest model image of each image into (best_idx, best_dist)
-    in place and return them.  FP32 mode: float32 (M, P) / (n_img, P) rows
-    and their norms.  BF16 mode: the outputs of ``bf16_centred`` for both
-    sides (one centre), plus the float32 rows and optional per-image
-    ``flags`` (int32, |= 1 where the FP32 fallback ran)."""
+def _match_operands(slices, slice_norm2, images, image_norm2, best_idx, best_dist, mode,
+                    slices_f32, images_f32, slice_err, image_err, flags):
     dt = torch.float32 if mode == MATCH_FP32 else torch.bfloat16
     dev = slices.device
     _need(slices, "slices", dt, dev)
@@ -319,6 +310,23 @@ def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
         _need(image_err, "image_err", torch.float32, dev, (n_img,))
         if flags is not None:
             _need(flags, "flags", torch.int32, dev, (n_img,))
+    return dev, M, n_img, P
+
+
+def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
+          image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
+          m_offset: int = 0, mode: int = MATCH_FP32, slices_f32: Optional[torch.Tensor] = None,
+          images_f32: Optional[torch.Tensor] = None, slice_err: Optional[torch.Tensor] = None,
+          image_err: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None,
+          workspace: Optional[torch.Tensor] = None) -> tuple:
+    """Fold the nearest model image of each image into (best_idx, best_dist)
+    in place and return them.  FP32 mode: float32 (M, P) / (n_img, P) rows
+    and their norms.  BF16 mode: the outputs of ``bf16_centred`` for both
+    sides (one centre), plus the float32 rows and optional per-image
+    ``flags`` (int32, |= 1 where the FP32 fallback ran)."""
+    dev, M, n_img, P = _match_operands(slices, slice_norm2, images, image_norm2, best_idx,
+                                       best_dist, mode, slices_f32, images_f32, slice_err,
+                                       image_err, flags)
     need = match_workspace_bytes(M, n_img, P, mode)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty((need,), dtype=torch.uint8, device=dev)
@@ -326,6 +334,29 @@ def match(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
                                  n_img, P, m_offset, mode, _p(slices_f32), _p(images_f32),
                                  _p(slice_err), _p(image_err), _p(best_idx), _p(best_dist),
                                  _p(flags), _p(workspace), workspace.numel(), _stream(dev)))
+    return best_idx, best_dist
+
+
+def match_noalloc(slices: torch.Tensor, slice_norm2: torch.Tensor, images: torch.Tensor,
+                  image_norm2: torch.Tensor, best_idx: torch.Tensor, best_dist: torch.Tensor,
+                  m_offset: int = 0, mode: int = MATCH_FP32,
+                  slices_f32: Optional[torch.Tensor] = None,
+                  images_f32: Optional[torch.Tensor] = None,
+                  slice_err: Optional[torch.Tensor] = None,
+                  image_err: Optional[torch.Tensor] = None,
+                  flags: Optional[torch.Tensor] = None) -> tuple:
+    """``match`` through spfel_match_noalloc: the workspace is the library's
+    per-device scratch array (nothing is allocated; calls that overlap on
+    one GPU race)."""
+    dev, M, n_img, P = _match_operands(slices, slice_norm2, images, image_norm2, best_idx,
+                                       best_dist, mode, slices_f32, images_f32, slice_err,
+                                       image_err, flags)
+    with torch.cuda.device(dev):
+        check(_lib.lib().spfel_match_noalloc(_p(slices), _p(slice_norm2), _p(images),
+                                             _p(image_norm2), M, n_img, P, m_offset, mode,
+                                             _p(slices_f32), _p(images_f32), _p(slice_err),
+                                             _p(image_err), _p(best_idx), _p(best_dist),
+                                             _p(flags), _stream(dev)))
     return best_idx, best_dist
 
 

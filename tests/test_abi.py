@@ -135,3 +135,15 @@ def test_row_norm2_validation():
 def test_exceptions_map_codes():
     with pytest.raises(spfel.SpfelInvalidArgument):
         _lib.check(spfel.lib().spfel_row_norm2(None, 7, 1, 1, None, None))
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch_before_any_launch():
+    L = spfel.lib()
+    p = ctypes.c_void_p(4096)
+    # BF16 candidates of 100,000 model images x 100,000 images: 2.5 GB > 64 MiB
+    code = L.spfel_match_noalloc(p, p, p, p, 100000, 100000, 64, 0, 1, p, p, p, p, p, p, None,
+                                 None)
+    assert code == _lib.ERANGE
+    assert "scratch" in L.spfel_last_error().decode()
+    assert L.spfel_match_noalloc(p, p, p, p, -1, 10, 64, 0, 0, None, None, None, None, p, p,
+                                 None, None) == _lib.EINVAL
