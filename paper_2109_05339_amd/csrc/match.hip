@@ -696,16 +696,27 @@ hipError_t launch_match_bf16(const uint16_t *S, const uint16_t *D, const float *
 
 // Bounds of the certified rescore (float32 arithmetic; every bound carries
 // a relative margin of 2^-16, far above the few roundings in its formula).
-//   proxy b~ = |s^|^2 + |d^|^2 - 2 s^.d^ computed on the matrix cores;
-//     |b~ - |s^ - d^|^2| <= A = g_acc (|s^| + |d^|)^2, g_acc = gamma_{P+64}
-//     at u = 2^-23 (every product added with its own rounding, whatever the
-//     hardware's internal order and rounding mode);
+//   proxy b~ = |s^|^2 + |d^|^2 - 2 s^.d^ with the dot product accumulated
+//     on the matrix cores: each v_mfma_f32_32x32x16_bf16 is taken as a tree
+//     of its 16 exact products plus the add to the accumulator, every
+//     rounding at most 2^-23 relative (truncation allowed), so a product
+//     meets at most P/16 + 8 roundings:
+//       |s^.d^ computed - s^.d^| <= g_acc sum_p |s^_p d^_p| <= g_acc |s^| |d^|,
+//     g_acc = gamma_{P/16+8} at u = 2^-23 (a probe of the instruction on
+//     random, wide-exponent and cancelling inputs measured at most
+//     3.2 x 2^-24 (|C| + sum |p|) per instruction).  The norms (float32
+//     sums of P/256 + 8 roundings) and the epilogue's two roundings add at
+//     most g_n (|s^| + |d^|)^2, g_n = gamma_{P/256+24} at u = 2^-24:
+//       A = 2 g_acc |s^| |d^| + g_n (|s^| + |d^|)^2 >= |b~ - |s^ - d^|^2|;
 //   true distance D = |s - d|^2:  |sqrt(D) - |s^ - d^|| <= e_m + f_n;
 //   float32 rescore D~ of D (direct sum of (s - d)^2, chains of at most
 //     P/64 + 16 roundings):  |D~ - D| <= g_run D.
 struct CertBounds {
-  float g_acc, g_run;
+  float g_acc, g_n, g_run;
 };
+__device__ inline float proxy_slack(const CertBounds &cb, float ns, float nd) {
+  return 2.0f * cb.g_acc * ns * nd + cb.g_n * (ns + nd) * (ns + nd);
+}
 constexpr float kLo = 1.0f - 0x1p-16f, kHi = 1.0f + 0x1p-16f;
 
 __device__ inline float lower_sqrt_dist(float b_lo, float A, float ef) {
@@ -831,7 +842,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(
     mi[s] = valid[s] ? (int)(uint32_t)(top[s] & 0xffffffffu) : 0;
     const uint32_t key = (uint32_t)(top[s] >> 32);
     const float ns = sqrtf(fmaxf(sn[mi[s]], 0.f));
-    const float A = cb.g_acc * (ns + nd) * (ns + nd);
+    const float A = proxy_slack(cb, ns, nd);
     const float ef = se[mi[s]] + fd;
     lb[s] = lower_sqrt_dist(key_float(key), A, ef);
     if (valid[s]) ub_min = fminf(ub_min, upper_sqrt_dist(key_float(key | low), A, ef));
@@ -864,7 +875,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(
   // certificate: only needed when model images lie outside the 8
   bool cert = true;
   if (M > 8) {
-    const float A8 = cb.g_acc * (stats[0] + nd) * (stats[0] + nd);
+    const float A8 = proxy_slack(cb, stats[0], nd);
     const float lb8 = lower_sqrt_dist(key_float((uint32_t)(top[7] >> 32)), A8, stats[1] + fd);
     cert = lb8 > upper_sqrt_rescored(key_float((uint32_t)(now >> 32)), cb.g_run);
   }
@@ -953,7 +964,8 @@ hipError_t launch_rescore(const uint32_t *cand, int tile_rows, int64_t M, int64_
   int32_t *list = reinterpret_cast<int32_t *>(w + 256);
   auto *keys = reinterpret_cast<unsigned long long *>(w + 256 + (((size_t)N * 4 + 255) & ~(size_t)255));
   CertBounds cb;
-  cb.g_acc = (float)gamma_of((double)P + 64.0, 0x1p-23);
+  cb.g_acc = (float)gamma_of((double)(P / 16) + 8.0, 0x1p-23);
+  cb.g_n = (float)gamma_of((double)(P / 256) + 24.0, 0x1p-24);
   cb.g_run = (float)gamma_of((double)(P / 64) + 16.0, 0x1p-24);
   hipError_t e = launch_fill_zero(count, 4, s);
   if (e != hipSuccess) return e;
