@@ -258,14 +258,16 @@ int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
 
 /* Weighted residual of slices against images (the gradient's spread input
  * for the weighted loss of Eq. (2)'s D-weighted least squares):
- *   residual[i] = scale * w_i * (s_i - d_i)        (may be NULL)
- *   *loss += sum_i w_i |s_i - d_i|^2               (float64, may be NULL)
+ *   residual[i] = scale * (*scale_dev) * w_i * (s_i - d_i)   (may be NULL)
+ *   *loss += sum_i w_i |s_i - d_i|^2                         (may be NULL)
  * over `count` elements (float32 or complex64 per the plan's domain;
- * weights NULL means 1).  The loss sum has a fixed order. */
+ * weights NULL means 1; scale_dev a device float32 scalar or NULL for 1, so
+ * a factor computed on the device needs no host round trip).  The loss is a
+ * device float64 scalar accumulated in float64 in a fixed order. */
 int spfel_weighted_residual(spfel_plan plan, const void *slices,
                             const void *images, const float *weights,
-                            int64_t count, float scale, void *residual,
-                            double *loss, void *stream);
+                            int64_t count, float scale, const float *scale_dev,
+                            void *residual, double *loss, void *stream);
 
 #ifdef __cplusplus
 }

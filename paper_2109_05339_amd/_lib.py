@@ -63,7 +63,7 @@ SIGNATURES = {
     "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _int, _i64,
                             _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "spfel_merge_adjoint": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _int, _vp]),
-    "spfel_weighted_residual": (_int, [_vp, _vp, _vp, _vp, _i64, _flt, _vp, _vp, _vp]),
+    "spfel_weighted_residual": (_int, [_vp, _vp, _vp, _vp, _i64, _flt, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None

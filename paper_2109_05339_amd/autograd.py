@@ -55,7 +55,8 @@ class SliceLossFn(torch.autograd.Function):
     def backward(ctx, grad_loss):
         model, quats, det_q, images, weights = ctx.saved_tensors
         plan, chunk = ctx.plan, ctx.chunk
-        scale = 2.0 * float(grad_loss)
+        # the incoming factor stays on the device (no host round trip)
+        g_dev = grad_loss.detach().to(torch.float32).reshape(1).contiguous()
         plan.set_model(model.contiguous())
         n = quats.shape[0]
         grad = None
@@ -63,7 +64,8 @@ class SliceLossFn(torch.autograd.Function):
             c1 = min(n, c0 + chunk)
             s, _ = plan.slice(quats[c0:c1], det_q)
             w = None if weights is None else weights[c0:c1]
-            r, _ = plan.weighted_residual(s, images[c0:c1], w, scale=scale, residual=True)
+            r, _ = plan.weighted_residual(s, images[c0:c1], w, scale=2.0, residual=True,
+                                          scale_dev=g_dev)
             del s
             last = c1 == n
             grad = plan.merge_adjoint(quats[c0:c1], det_q, r,

@@ -744,8 +744,8 @@ int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
 
 int spfel_weighted_residual(spfel_plan plan, const void *slices,
                             const void *images, const float *weights,
-                            int64_t count, float scale, void *residual,
-                            double *loss, void *stream) {
+                            int64_t count, float scale, const float *scale_dev,
+                            void *residual, double *loss, void *stream) {
   clear_error();
   Plan *p = reinterpret_cast<Plan *>(plan);
   if (!live(p)) return fail(SPFEL_ESTATE, "weighted_residual: not a live plan");
@@ -756,11 +756,12 @@ int spfel_weighted_residual(spfel_plan plan, const void *slices,
   if (!slices || !images) return fail(SPFEL_EINVAL, "weighted_residual: NULL input");
   const size_t a = cplx ? 8 : 4;
   if (!aligned(slices, a) || !aligned(images, a) || (residual && !aligned(residual, a)) ||
-      (weights && !aligned(weights, 4)) || (loss && !aligned(loss, 8)))
+      (weights && !aligned(weights, 4)) || (loss && !aligned(loss, 8)) ||
+      (scale_dev && !aligned(scale_dev, 4)))
     return fail(SPFEL_EINVAL, "weighted_residual: misaligned pointer");
   DeviceGuard g(p->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "weighted_residual: hipSetDevice");
-  hipError_t e = launch_residual(cplx, slices, images, weights, count, scale, residual,
+  hipError_t e = launch_residual(cplx, slices, images, weights, count, scale, scale_dev, residual,
                                  p->partials, loss, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "weighted_residual: launch");
 }

@@ -130,7 +130,7 @@ hipError_t launch_bf16_centred(const float *x, int64_t rows, int64_t cols,
 
 hipError_t launch_residual(bool cplx, const void *s, const void *d,
                            const float *w, int64_t count, float scale,
-                           void *r, double *partials, double *loss,
-                           hipStream_t st);
+                           const float *scale_dev, void *r, double *partials,
+                           double *loss, hipStream_t st);
 
 }  // namespace spfel

@@ -1,6 +1,9 @@
-// Weighted residual r = scale w (s - d) and loss sum w |s - d|^2 of slices
-// against images: the data term of the D-weighted least squares behind
-// merging (section II-C, Eq. (1)-(2)); its spread is the loss gradient.
+// Weighted residual r = scale (*scale_dev) w (s - d) and loss sum w |s - d|^2
+// of slices against images: the data term of the D-weighted least squares
+// behind merging (section II-C, Eq. (1)-(2)); its spread is the loss
+// gradient.  The loss accumulates in float64: the scalar is differenced in
+// finite-difference checks far below float32 resolution of a sum of 10^7 -
+// 10^8 terms (one float64 add per element; the kernel is bound by HBM).
 #include "internal.h"
 
 namespace spfel {
@@ -10,8 +13,10 @@ constexpr int kResThreads = 256;
 template <bool CPLX>
 __global__ __launch_bounds__(kResThreads) void residual_kernel(
     const void *__restrict__ s_, const void *__restrict__ d_, const float *__restrict__ w,
-    int64_t count, float scale, void *__restrict__ r_, double *__restrict__ partials) {
+    int64_t count, float scale, const float *__restrict__ scale_dev, void *__restrict__ r_,
+    double *__restrict__ partials) {
   __shared__ double sh[kResThreads];
+  if (scale_dev) scale *= *scale_dev;
   const int64_t per = (count + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = min(count, lo + per);
@@ -50,16 +55,17 @@ __global__ void loss_finish_kernel(const double *__restrict__ partials, int n,
 }
 
 hipError_t launch_residual(bool cplx, const void *s, const void *d, const float *w, int64_t count,
-                           float scale, void *r, double *partials, double *loss, hipStream_t st) {
+                           float scale, const float *scale_dev, void *r, double *partials,
+                           double *loss, hipStream_t st) {
   int64_t blocks = (count + 4 * kResThreads - 1) / (4 * kResThreads);
   if (blocks > kMaxPartials) blocks = kMaxPartials;
   if (blocks < 1) blocks = 1;
   if (cplx)
     hipLaunchKernelGGL((residual_kernel<true>), dim3((unsigned)blocks), dim3(kResThreads), 0, st, s,
-                       d, w, count, scale, r, partials);
+                       d, w, count, scale, scale_dev, r, partials);
   else
     hipLaunchKernelGGL((residual_kernel<false>), dim3((unsigned)blocks), dim3(kResThreads), 0, st,
-                       s, d, w, count, scale, r, partials);
+                       s, d, w, count, scale, scale_dev, r, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !loss) return e;
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, st, partials, (int)blocks, loss);

@@ -200,21 +200,27 @@ class Plan:
 
     def weighted_residual(self, slices: torch.Tensor, images: torch.Tensor,
                           weights: Optional[torch.Tensor] = None, scale: float = 1.0,
-                          residual: bool = True, loss: Optional[torch.Tensor] = None):
-        """residual = scale w (s - d) (or None) and loss += sum w |s - d|^2
-        (a float64 device scalar, created if not given)."""
+                          residual: bool = True, loss: Optional[torch.Tensor] = None,
+                          scale_dev: Optional[torch.Tensor] = None):
+        """residual = scale * scale_dev * w (s - d) (or None) and
+        loss += sum w |s - d|^2 (a float64 device scalar, created if not
+        given).  ``scale_dev``: optional float32 device scalar."""
         _need(slices, "slices", self.cdtype, self.device)
         _need(images, "images", self.cdtype, self.device, tuple(slices.shape))
         if weights is not None:
             _need(weights, "weights", torch.float32, self.device, tuple(slices.shape))
+        if scale_dev is not None:
+            _need(scale_dev, "scale_dev", torch.float32, self.device)
+            if scale_dev.numel() != 1:
+                raise ValueError("scale_dev must hold one value")
         if loss is None:
             loss = torch.zeros((), dtype=torch.float64, device=self.device)
         else:
             _need(loss, "loss", torch.float64, self.device)
         r = torch.empty_like(slices) if residual else None
         check(_lib.lib().spfel_weighted_residual(self._h, _p(slices), _p(images), _p(weights),
-                                                 slices.numel(), float(scale), _p(r), _p(loss),
-                                                 _stream(self.device)))
+                                                 slices.numel(), float(scale), _p(scale_dev),
+                                                 _p(r), _p(loss), _stream(self.device)))
         return r, loss
 
 

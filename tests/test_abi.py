@@ -67,7 +67,7 @@ def test_dead_plan_handles_are_rejected():
     assert L.spfel_set_model(bogus, bogus, None) == _lib.ESTATE
     assert L.spfel_slice(bogus, None, 1, None, 1, None, None, None, None) == _lib.ESTATE
     assert L.spfel_merge_adjoint(bogus, None, 1, None, 1, None, None, None, 0, None) == _lib.ESTATE
-    assert L.spfel_weighted_residual(bogus, None, None, None, 1, 1.0, None, None, None) == _lib.ESTATE
+    assert L.spfel_weighted_residual(bogus, None, None, None, 1, 1.0, None, None, None, None) == _lib.ESTATE
     assert L.spfel_plan_info(bogus, None, None) == _lib.ESTATE
     with pytest.raises(spfel.SpfelStateError):
         _lib.check(L.spfel_plan_destroy(bogus))

@@ -94,3 +94,17 @@ def test_slice_loss_with_registered_detector():
     assert abs(float(L.detach()) - Lref) <= 1e-4 * Lref
     gref = ograd.grad(m64, x, d.astype(np.complex128).ravel(), f32(w).ravel())
     assert rel(host(mt.grad), gref) <= 1e-4
+
+
+def test_upstream_gradient_scales_on_the_device():
+    """backward of c * L passes c to the residual as a device scalar: the
+    gradient is c times that of L."""
+    m, q, det, x, d, w = setup(n_img=5)
+    plan = spfel.Plan(13, domain=spfel.COMPLEX, device=DEV)
+    grads = []
+    for c in (1.0, -2.5):
+        mt = gpu(m, torch.complex64).requires_grad_(True)
+        L = spfel.slice_loss(mt, gpu(q), gpu(det), gpu(d, torch.complex64), gpu(w), plan, chunk=2)
+        (c * L).backward()
+        grads.append(host(mt.grad))
+    assert rel(grads[1], -2.5 * grads[0]) <= 1e-6
