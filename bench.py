@@ -81,7 +81,7 @@ KERNEL_SOURCES = {
     "interp_tiled_kernel": ["interp.hip", "device_common.h", "internal.h"],
     "match_f32_kernel": ["match.hip", "device_common.h", "internal.h"],
     "match_bf16_big_kernel": ["match.hip", "device_common.h", "internal.h"],
-    "spread_mfma_kernel": ["spread.hip", "device_common.h", "internal.h"],
+    "spread_binned_kernel": ["spread_binned.hip", "device_common.h", "internal.h"],
 }
 COPY_BYTES = 1 << 30
 
@@ -326,9 +326,9 @@ def bench_streaming(args, cfg, dev):
     r_match = roofline("match_bf16_big_kernel + rescore", "mfma", 2.0 * C * n_img * P,
                        per["match"], PEAK_BF16_MFMA_TFLOPS, "TFLOP/s",
                        traffic_of("match_bf16_big_kernel", 5))
-    r_merge = roofline("spread_mfma_kernel + transform", "alu", INTERP_FLOP_PER_POINT * n_img * P,
+    r_merge = roofline("binned spread + transform", "alu", INTERP_FLOP_PER_POINT * n_img * P,
                        per["merge"], PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s",
-                       traffic_of("spread_mfma_kernel", 5))
+                       traffic_of("spread_binned_kernel", 5))
     share = {"slice": tot["slice"], "match": tot["match"], "merge": tot["merge"]}
     dominant = {"slice": r_slice, "match": r_match, "merge": r_merge}[max(share, key=share.get)]
     fl = flags.cpu().numpy()

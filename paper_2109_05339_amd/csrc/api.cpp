@@ -163,7 +163,55 @@ static bool aligned(const void *p, size_t a) {
   return (reinterpret_cast<uintptr_t>(p) % a) == 0;
 }
 
+static void free_bins(Plan *p) {
+  void *bufs[] = {p->bin_pts, p->bin_aux, p->bin_off, p->bin_cur, p->bin_part, p->bin_sub,
+                  p->bin_nsub};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  p->bin_pts = nullptr;
+  p->bin_aux = nullptr;
+  p->bin_off = p->bin_cur = p->bin_part = p->bin_nsub = nullptr;
+  p->bin_sub = nullptr;
+  p->bin_cap = p->bin_batch = 0;
+}
+
+// Scratch of the binned spread for detectors of P points: batches of up to
+// 2^26 points (and at most 65,536 images), key counts and offsets,
+// subproblem list.  Returns the bytes allocated, or 0 on failure (nothing
+// kept).
+static size_t alloc_bins(Plan *p, int64_t P) {
+  const int64_t per = std::max<int64_t>(1, std::min<int64_t>(kBinBatchPoints / P, 65536));
+  const int64_t cap = per * P;
+  const size_t keys = bin_keys(p->nf, p->w);
+  const size_t parts = (keys + 1023) / 1024;
+  const size_t subs = bin_max_subproblems(p->nf, p->w, cap);
+  struct Req {
+    void **ptr;
+    size_t bytes;
+  } reqs[] = {{reinterpret_cast<void **>(&p->bin_pts), (size_t)cap * sizeof(float4)},
+              {reinterpret_cast<void **>(&p->bin_aux), (size_t)cap * sizeof(uint2)},
+              {reinterpret_cast<void **>(&p->bin_off), (keys + 1) * sizeof(int32_t)},
+              {reinterpret_cast<void **>(&p->bin_cur), keys * sizeof(int32_t)},
+              {reinterpret_cast<void **>(&p->bin_part), parts * sizeof(int32_t)},
+              {reinterpret_cast<void **>(&p->bin_sub), subs * sizeof(int4)},
+              {reinterpret_cast<void **>(&p->bin_nsub), 256}};
+  size_t total = 0;
+  for (auto &r : reqs) {
+    if (hipMalloc(r.ptr, r.bytes) != hipSuccess) {
+      *r.ptr = nullptr;
+      (void)hipGetLastError();
+      free_bins(p);
+      return 0;
+    }
+    total += r.bytes;
+  }
+  p->bin_cap = cap;
+  p->bin_batch = per;
+  return total;
+}
+
 static void free_plan(Plan *p) {
+  free_bins(p);
   void *bufs[] = {p->u, p->wpos, p->wneg, p->t1, p->t2, p->acc, p->partials, p->rot,
                   p->det_sorted, p->det_perm};
   for (void *b : bufs)
@@ -413,7 +461,23 @@ int spfel_set_detector(spfel_plan plan, const float *det_q, int64_t P, void *str
     p->bytes -= (size_t)p->det_P * 3 * sizeof(float) + (size_t)p->det_P * sizeof(int32_t);
     (void)hipFree(p->det_sorted);
     (void)hipFree(p->det_perm);
+    p->det_sorted = nullptr;
+    p->det_perm = nullptr;
+    p->det_P = 0;
   }
+  if (p->bin_cap) {
+    p->bytes -= p->bin_bytes;
+    free_bins(p);
+    p->bin_bytes = 0;
+  }
+  const size_t bb = alloc_bins(p, P);
+  if (bb == 0) {
+    (void)hipFree(ds);
+    (void)hipFree(dp);
+    return fail(SPFEL_ENOMEM, "set_detector: hipMalloc of the spreading scratch");
+  }
+  p->bin_bytes = bb;
+  p->bytes += bb;
   p->det_sorted = ds;
   p->det_perm = dp;
   p->det_P = P;

@@ -45,6 +45,19 @@ struct Plan {
   float *det_sorted = nullptr;   // det_P x 3
   int32_t *det_perm = nullptr;   // det_P
   int64_t det_P = 0;
+  // Binned spreading over the registered detector (allocated with it):
+  // points of up to bin_batch images at a time, grouped by the fine-grid
+  // bin of their support origin and their axis-1 origin (the key).
+  float4 *bin_pts = nullptr;     // bin_cap: value (re), three kernel offsets
+  uint2 *bin_aux = nullptr;      // bin_cap: packed origin in the brick, value (im) bits
+  int32_t *bin_off = nullptr;    // keys + 1: counts, then exclusive offsets
+  int32_t *bin_cur = nullptr;    // keys: scatter cursors
+  int32_t *bin_part = nullptr;   // scan block totals
+  int4 *bin_sub = nullptr;       // subproblems (bin, first point, end)
+  int32_t *bin_nsub = nullptr;   // number of subproblems
+  int64_t bin_cap = 0;           // points per batch
+  int64_t bin_batch = 0;         // images per batch
+  size_t bin_bytes = 0;
   bool model_set = false;
   bool pending = false;  // deferred spreads are waiting in acc
   size_t bytes = 0;
@@ -59,6 +72,13 @@ struct Plan {
 constexpr int kTile = 256;
 // Orientations per slicing launch (size of Plan::rot).
 constexpr int64_t kRotCap = 65536;
+// Binned spreading: brick side (cells), points per subproblem, points per
+// batch of images.
+constexpr int kBrick = 16;
+constexpr int kSubMax = 8192;
+constexpr int64_t kBinBatchPoints = (int64_t)1 << 26;
+size_t bin_keys(int nf, int w);
+size_t bin_max_subproblems(int nf, int w, int64_t cap);
 
 // Status helpers: set the thread-local message and return the code.
 int fail(int code, const std::string &msg);
@@ -83,13 +103,20 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 // detq == nullptr selects the plan's registered detector (tiled kernel).
 hipError_t launch_interp(const Plan &pl, const float *quats, int64_t M,
                          const float *detq, int64_t P, void *out, hipStream_t s);
+// rot[9 m + 3 d + e] = R(quats[m])[d][e] * scale (float64; NaN for a zero
+// or non-finite quaternion), M <= kRotCap.
+hipError_t launch_rotations(const float *quats, int64_t M, double scale, double *rot,
+                            hipStream_t s);
 hipError_t launch_row_norm2(const void *x, bool bf16, int64_t rows,
                             int64_t cols, float *out, hipStream_t s);
 
-// detq == nullptr selects the plan's registered detector (tiled kernel).
+// detq == nullptr selects the plan's registered detector (binned spread).
 hipError_t launch_spread(const Plan &pl, const float *quats, int64_t n_img,
                          const float *detq, int64_t P, const void *values,
                          const float *weights, hipStream_t s);
+hipError_t launch_spread_binned(const Plan &pl, const float *quats, int64_t n_img,
+                                int64_t P, const void *values, const float *weights,
+                                hipStream_t s);
 
 hipError_t launch_pack_keys(const int32_t *idx, const float *dist,
                             unsigned long long *keys, int64_t n,

@@ -22,6 +22,14 @@ __global__ __launch_bounds__(256) void rotation_kernel(const float *__restrict__
   for (int k = 0; k < 9; ++k) rot[9 * m + k] = ok ? R[k] * scale : nan;
 }
 
+hipError_t launch_rotations(const float *quats, int64_t M, double scale, double *rot,
+                            hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rotation_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, quats, M,
+                     scale, rot);
+  return hipGetLastError();
+}
+
 template <int W, bool CPLX>
 __global__ __launch_bounds__(256) void interp_gather_kernel(
     const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
