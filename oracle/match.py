@@ -41,6 +41,20 @@ def distances_expanded(S, D) -> np.ndarray:
     return sn[:, None] + dn[None, :] - 2.0 * (S @ D.T)
 
 
+def distances_weighted(S, D, w) -> np.ndarray:
+    """D_w[m, n] = sum_p w_p (S[m,p] - D[n,p])^2 with per-pixel weights
+    w_p >= 0 (the weights D of Eq. (2); a beam-stop mask is w_p in {0, 1}),
+    summed directly in FP64."""
+    S = np.asarray(S, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    out = np.empty((S.shape[0], D.shape[0]))
+    for n in range(D.shape[0]):
+        diff = S - D[n][None, :]
+        out[:, n] = (diff * diff * w[None, :]).sum(axis=1)
+    return out
+
+
 def argmin_first(Dmat) -> np.ndarray:
     """Per image (column), the lowest m attaining the minimum distance."""
     return np.argmin(np.asarray(Dmat), axis=0).astype(np.int64)

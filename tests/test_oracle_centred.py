@@ -106,3 +106,32 @@ def test_certificate_fails_where_bf16_cannot_separate():
     ex = match.distances_direct(S, D)
     cert = match.centred_certificate(match.centred_proxy(Sv, Dv), e, f, ex, k=8)
     np.testing.assert_array_equal(cert, [False, True])
+
+
+def test_weighted_distances_pins():
+    """Per-pixel weights (Eq. (2)'s D; a beam-stop mask is 0/1): unit weights
+    give the plain distances; a brute-force double loop agrees; values at
+    masked pixels do not matter; scaling one pixel's weight by t scales its
+    contribution by t."""
+    g = np.random.default_rng(7)
+    S = g.gamma(2.0, 10.0, (9, 40))
+    D = g.poisson(S[[1, 4, 7]]).astype(np.float64)
+    np.testing.assert_allclose(match.distances_weighted(S, D, np.ones(40)),
+                               match.distances_direct(S, D), rtol=1e-14)
+    w = g.uniform(0.0, 2.0, 40)
+    ref = np.zeros((9, 3))
+    for m in range(9):
+        for n in range(3):
+            for p in range(40):
+                ref[m, n] += w[p] * (S[m, p] - D[n, p]) ** 2
+    np.testing.assert_allclose(match.distances_weighted(S, D, w), ref, rtol=1e-13)
+    mask = np.ones(40)
+    mask[10:20] = 0.0
+    D2 = D.copy()
+    D2[:, 10:20] = 1e6
+    np.testing.assert_array_equal(match.distances_weighted(S, D, mask),
+                                  match.distances_weighted(S, D2, mask))
+    w2 = w.copy()
+    w2[3] *= 5.0
+    delta = match.distances_weighted(S, D, w2) - match.distances_weighted(S, D, w)
+    np.testing.assert_allclose(delta, 4.0 * w[3] * (S[:, 3:4] - D[:, 3][None, :]) ** 2, rtol=1e-10)
