@@ -150,6 +150,14 @@ int spfel_bf16_centred(const float *x, int64_t rows, int64_t cols,
                        const float *centre, uint16_t *out, float *norm2,
                        float *err, void *stream);
 
+/* Per-pixel weights of the distance (section II-C: the weights D of Eq. (2);
+ * a beam stop's missing detector centre is weight 0): out[r][p] =
+ * x[r][p] * g[p] for rows x cols float32 x and g[p] = sqrt(w_p).  Matching
+ * rows scaled this way (model images and images alike) gives the weighted
+ * distance sum_p w_p (s_p - d_p)^2 in every matcher mode.  out may equal x. */
+int spfel_scale_columns(const float *x, int64_t rows, int64_t cols,
+                        const float *g, float *out, void *stream);
+
 /* Bytes of device workspace spfel_match needs for these sizes and mode. */
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P,
                                    int mode);
@@ -220,7 +228,10 @@ size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
  * two workspace buffers while the previous chunk is matched on `stream`; the
  * model slices are never stored in full.  The result equals spfel_slice of
  * each chunk (and, in BF16 mode, spfel_bf16_centred of it with `centre`)
- * followed by spfel_match with m_offset = chunk start.  REAL plans only;
+ * followed by spfel_match with m_offset = chunk start; pixel_scale (P
+ * float32 or NULL) scales each chunk's columns as spfel_scale_columns before
+ * the norms and the centring, for weighted distances (the images must be
+ * scaled the same way by the caller).  REAL plans only;
  * requires spfel_set_model.  FP32 mode: images n_img x P float32 with their
  * norms; centre, images_f32, image_err and flags ignored.  BF16 mode: images,
  * image_norm2, image_err from spfel_bf16_centred of images_f32 with
@@ -230,12 +241,13 @@ size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P,
  * overlap).  workspace: spfel_orient_workspace_bytes, 256-byte aligned;
  * calls that overlap on the same plan race. */
 int spfel_orient(spfel_plan plan, const float *quats, int64_t M,
-                 const float *det_q, int64_t P, const void *images,
-                 const float *image_norm2, const float *images_f32,
-                 const float *image_err, const float *centre, int64_t n_img,
-                 int mode, int64_t chunk, int32_t *best_idx, float *best_dist,
-                 int32_t *flags, void *workspace, size_t workspace_bytes,
-                 void *stream, void *aux_stream);
+                 const float *det_q, int64_t P, const float *pixel_scale,
+                 const void *images, const float *image_norm2,
+                 const float *images_f32, const float *image_err,
+                 const float *centre, int64_t n_img, int mode, int64_t chunk,
+                 int32_t *best_idx, float *best_dist, int32_t *flags,
+                 void *workspace, size_t workspace_bytes, void *stream,
+                 void *aux_stream);
 
 /* Section II-C, Eq. (2) right-hand side: the type-1 NUFFT (adjoint of
  * slicing) of values at the points R(quats[n]) det_q[p] (det_q NULL: the

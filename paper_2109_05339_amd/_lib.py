@@ -60,8 +60,9 @@ SIGNATURES = {
     "spfel_match_noalloc": (_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _int, _vp, _vp,
                                    _vp, _vp, _vp, _vp, _vp, _vp]),
     "spfel_orient_workspace_bytes": (_sz, [_i64, _i64, _i64, _int]),
-    "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _int, _i64,
-                            _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "spfel_orient": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _int,
+                            _i64, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "spfel_scale_columns": (_int, [_vp, _i64, _i64, _vp, _vp, _vp]),
     "spfel_merge_adjoint": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _int, _vp]),
     "spfel_weighted_residual": (_int, [_vp, _vp, _vp, _vp, _i64, _flt, _vp, _vp, _vp, _vp]),
 }

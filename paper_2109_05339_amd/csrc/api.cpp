@@ -586,6 +586,18 @@ int spfel_bf16_centred(const float *x, int64_t rows, int64_t cols, const float *
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "bf16_centred: launch");
 }
 
+int spfel_scale_columns(const float *x, int64_t rows, int64_t cols, const float *g, float *out,
+                        void *stream) {
+  clear_error();
+  if (rows < 0 || cols < 0) return fail(SPFEL_EINVAL, "scale_columns: negative size");
+  if (rows == 0 || cols == 0) return SPFEL_OK;
+  if (!x || !g || !out) return fail(SPFEL_EINVAL, "scale_columns: NULL pointer");
+  if (!aligned(x, 4) || !aligned(g, 4) || !aligned(out, 4))
+    return fail(SPFEL_EINVAL, "scale_columns: misaligned pointer");
+  hipError_t e = launch_scale_columns(x, rows, cols, g, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SPFEL_OK : hip_fail(e, "scale_columns: launch");
+}
+
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t spfel_match_workspace_bytes(int64_t M, int64_t n_img, int64_t P, int mode) {
@@ -675,7 +687,8 @@ size_t spfel_orient_workspace_bytes(int64_t chunk, int64_t n_img, int64_t P, int
 }
 
 int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *det_q, int64_t P,
-                 const void *images, const float *image_norm2, const float *images_f32,
+                 const float *pixel_scale, const void *images, const float *image_norm2,
+                 const float *images_f32,
                  const float *image_err, const float *centre, int64_t n_img, int mode,
                  int64_t chunk, int32_t *best_idx, float *best_dist, int32_t *flags,
                  void *workspace, size_t workspace_bytes, void *stream, void *aux_stream) {
@@ -698,6 +711,7 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
   if (bf && (!images_f32 || !image_err))
     return fail(SPFEL_EINVAL, "orient: BF16 mode needs images_f32 and image_err");
   if (bf && centre && !aligned(centre, 4)) return fail(SPFEL_EINVAL, "orient: centre misaligned");
+  if (pixel_scale && !aligned(pixel_scale, 4)) return fail(SPFEL_EINVAL, "orient: pixel_scale misaligned");
   if (m_offset_overflow(M)) return fail(SPFEL_ERANGE, "orient: model index exceeds int32");
   if (chunk > M) chunk = M;
   const size_t need = spfel_orient_workspace_bytes(chunk, n_img, P, mode);
@@ -737,8 +751,14 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M, const float *de
       e = hipStreamWaitEvent(a, p->ev_matched[k], 0);
       if (e != hipSuccess) return hip_fail(e, "orient: event");
     }
-    rc = spfel_slice(plan, quats + 4 * m0, mc, det_q, P, st[k].f32, bf ? nullptr : st[k].norm, a);
+    rc = spfel_slice(plan, quats + 4 * m0, mc, det_q, P, st[k].f32,
+                     bf || pixel_scale ? nullptr : st[k].norm, a);
     if (rc != SPFEL_OK) return rc;
+    if (pixel_scale) {
+      rc = spfel_scale_columns(st[k].f32, mc, P, pixel_scale, st[k].f32, a);
+      if (rc == SPFEL_OK && !bf) rc = spfel_row_norm2(st[k].f32, SPFEL_F32, mc, P, st[k].norm, a);
+      if (rc != SPFEL_OK) return rc;
+    }
     if (bf) {
       rc = spfel_bf16_centred(st[k].f32, mc, P, centre, st[k].b16, st[k].norm, st[k].err, a);
       if (rc != SPFEL_OK) return rc;

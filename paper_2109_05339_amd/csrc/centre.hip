@@ -112,4 +112,41 @@ hipError_t launch_bf16_centred(const float *x, int64_t rows, int64_t cols, const
   return hipGetLastError();
 }
 
+// out[r][p] = x[r][p] g[p] (in place allowed).
+__global__ __launch_bounds__(256) void scale_columns_kernel(const float *x, int64_t rows,
+                                                            int64_t cols,
+                                                            const float *__restrict__ g, float *out,
+                                                            int vec) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    const int64_t q4 = cols / 4, n4 = rows * q4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+      const int64_t c4 = i % q4;
+      float4 v = reinterpret_cast<const float4 *>(x)[i];
+      const float4 s = reinterpret_cast<const float4 *>(g)[c4];
+      v.x *= s.x;
+      v.y *= s.y;
+      v.z *= s.z;
+      v.w *= s.w;
+      reinterpret_cast<float4 *>(out)[i] = v;
+    }
+  } else {
+    const int64_t n = rows * cols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+      out[i] = x[i] * g[i % cols];
+  }
+}
+
+hipError_t launch_scale_columns(const float *x, int64_t rows, int64_t cols, const float *g,
+                                float *out, hipStream_t s) {
+  auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const int vec = cols % 4 == 0 && al(x) && al(g) && al(out);
+  int64_t blocks = (rows * cols / (vec ? 4 : 1) + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, rows, cols,
+                     g, out, vec);
+  return hipGetLastError();
+}
+
 }  // namespace spfel

@@ -154,6 +154,8 @@ hipError_t launch_column_mean(const float *x, int64_t rows, int64_t cols,
 hipError_t launch_bf16_centred(const float *x, int64_t rows, int64_t cols,
                                const float *c, uint16_t *out, float *norm2,
                                float *err, hipStream_t s);
+hipError_t launch_scale_columns(const float *x, int64_t rows, int64_t cols,
+                                const float *g, float *out, hipStream_t s);
 
 hipError_t launch_residual(bool cplx, const void *s, const void *d,
                            const float *w, int64_t count, float scale,

@@ -192,7 +192,8 @@ class Plan:
             ws = torch.empty((need,), dtype=torch.uint8, device=self.device)
             self._orient_ws = ws
         ws.record_stream(aux)
-        check(_lib.lib().spfel_orient(self._h, _p(quats), M, _p(det_q), P, _p(ops_img), _p(n2),
+        check(_lib.lib().spfel_orient(self._h, _p(quats), M, _p(det_q), P, _p(images.g),
+                                      _p(ops_img), _p(n2),
                                       _p(f32), _p(err), _p(centre), n_img, mode, c,
                                       _p(best_idx), _p(best_dist), _p(flags), _p(ws), ws.numel(),
                                       main.cuda_stream, aux.cuda_stream))
@@ -265,23 +266,52 @@ def bf16_centred(x: torch.Tensor, centre: Optional[torch.Tensor] = None) -> tupl
     return out, n2, err
 
 
-class ImagesF32:
-    """Float32 matcher operand: rows and their squared norms."""
+def scale_columns(x: torch.Tensor, g: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x[r][p] * g[p] for a (rows, cols) float32 matrix: with g = sqrt(w),
+    matching scaled rows gives the per-pixel weighted distance
+    sum_p w_p (s_p - d_p)^2 (a beam stop is w_p = 0)."""
+    _need(x, "x", torch.float32, x.device)
+    if x.dim() != 2:
+        raise ValueError("scale_columns takes a matrix")
+    _need(g, "g", torch.float32, x.device, (x.shape[1],))
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _need(out, "out", torch.float32, x.device, tuple(x.shape))
+    check(_lib.lib().spfel_scale_columns(_p(x), x.shape[0], x.shape[1], _p(g), _p(out),
+                                         _stream(x.device)))
+    return out
 
-    def __init__(self, x: torch.Tensor):
-        self.x = x
-        self.norm2 = row_norm2(x)
+
+def _pixel_scale(pixel_weights, x):
+    if pixel_weights is None:
+        return None
+    w = torch.as_tensor(pixel_weights, dtype=torch.float32, device=x.device)
+    if w.shape != (x.shape[1],) or bool((w < 0).any()):
+        raise ValueError("pixel_weights must be (P,) and nonnegative")
+    return torch.sqrt(w).contiguous()
+
+
+class ImagesF32:
+    """Float32 matcher operand: rows (scaled by sqrt(pixel_weights) when
+    given) and their squared norms."""
+
+    def __init__(self, x: torch.Tensor, pixel_weights=None):
+        self.g = _pixel_scale(pixel_weights, x)
+        self.x = x if self.g is None else scale_columns(x, self.g)
+        self.norm2 = row_norm2(self.x)
 
 
 class ImagesBF16:
-    """BF16 matcher operand: the float32 rows, a centre (rounded column mean
-    of these rows unless given), and the centred BF16 rows with their norms
-    and rounding-error bounds."""
+    """BF16 matcher operand: the float32 rows (scaled by sqrt(pixel_weights)
+    when given), a centre (rounded column mean of those rows unless given),
+    and the centred BF16 rows with their norms and rounding-error bounds."""
 
-    def __init__(self, x: torch.Tensor, centre: Optional[torch.Tensor] = None):
-        self.x = x
-        self.centre = column_mean(x) if centre is None else centre
-        self.b16, self.norm2, self.err = bf16_centred(x, self.centre)
+    def __init__(self, x: torch.Tensor, centre: Optional[torch.Tensor] = None, pixel_weights=None):
+        self.g = _pixel_scale(pixel_weights, x)
+        self.x = x if self.g is None else scale_columns(x, self.g)
+        self.centre = column_mean(self.x) if centre is None else centre
+        self.b16, self.norm2, self.err = bf16_centred(self.x, self.centre)
 
 
 def match_workspace_bytes(M: int, n_img: int, P: int, mode: int = MATCH_FP32) -> int:
@@ -370,8 +400,10 @@ def match_bf16(slices_f32: torch.Tensor, images: "ImagesBF16", best_idx: torch.T
                best_dist: torch.Tensor, m_offset: int = 0, flags: Optional[torch.Tensor] = None,
                workspace: Optional[torch.Tensor] = None) -> tuple:
     """BF16 matching of float32 model images against prepared images:
-    centres the model images with the images' centre, then ``match``."""
-    sb, sn, se = bf16_centred(slices_f32, images.centre)
+    scales the model images' columns as the images' were, centres them with
+    the images' centre, then ``match``."""
+    s = slices_f32 if images.g is None else scale_columns(slices_f32, images.g)
+    sb, sn, se = bf16_centred(s, images.centre)
     return match(sb, sn, images.b16, images.norm2, best_idx, best_dist, m_offset=m_offset,
-                 mode=MATCH_BF16_RESCORE8, slices_f32=slices_f32, images_f32=images.x,
+                 mode=MATCH_BF16_RESCORE8, slices_f32=s, images_f32=images.x,
                  slice_err=se, image_err=images.err, flags=flags, workspace=workspace)
