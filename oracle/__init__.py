@@ -12,7 +12,8 @@ passage of the SpiniFEL paper (arXiv 2109.05339) it follows:
 * orientation matching, section II-B: every image against every model image,
   Euclidean distance, nearest model image wins;
 * merging, section II-C, Eq. (1)-(2): the type-1 NUFFT A* (with weights D)
-  as the adjoint of slicing.
+  as the adjoint of slicing, and the regularised normal equations of
+  Eq. (2) with their Toeplitz form, conjugate gradients and the L-curve.
 
 The paper fixes no NUFFT internals; it names the ES-kernel library of its
 reference [barnett2019parallel].  The readings used (kernel, width, shape
@@ -23,4 +24,4 @@ Parity status: every function below is pinned by a CPU test (closed forms,
 brute force, library routines or invariants), except where its docstring
 says "parity unpinned".
 """
-from . import es, geometry, nudft, nufft, match, grad  # noqa: F401
+from . import es, geometry, nudft, nufft, match, grad, normal  # noqa: F401
