@@ -94,13 +94,18 @@ def solve_dense(x, d, b, N: int, lam: float, x0, real: bool = False) -> np.ndarr
 
 def cg(apply_op, rhs, x0, iters: int):
     """Conjugate gradients for a Hermitian positive definite operator,
-    started at x0; returns (x, residual norms |r_i| for i = 0..iters)."""
+    started at x0; returns (x, residual norms |r_i| for i = 0..iters).
+    A residual that reaches exactly zero ends the iteration (x is then the
+    solution; later norms are recorded as 0)."""
     x = np.array(x0, dtype=np.result_type(rhs, x0, np.float64))
     r = rhs - apply_op(x)
     p = r.copy()
     rr = np.vdot(r, r).real
     hist = [np.sqrt(rr)]
     for _ in range(iters):
+        if rr == 0.0:
+            hist.append(0.0)
+            continue
         Ap = apply_op(p)
         alpha = rr / np.vdot(p, Ap).real
         x = x + alpha * p

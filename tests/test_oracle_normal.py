@@ -79,6 +79,19 @@ def test_cg_converges_to_the_dense_solution(real):
     np.testing.assert_allclose(xc, xs, rtol=1e-8, atol=1e-8 * np.abs(xs).max())
 
 
+def test_cg_stops_at_an_exact_solution():
+    # identity operator: one step reaches the solution exactly; a start at
+    # the solution has a zero residual from the outset
+    g = np.random.default_rng(8)
+    rhs = g.standard_normal((3, 3, 3))
+    x, hist = normal.cg(lambda v: v, rhs, np.zeros((3, 3, 3)), 5)
+    np.testing.assert_allclose(x, rhs, rtol=1e-15)
+    assert np.all(np.isfinite(hist)) and np.all(hist[2:] == 0.0)
+    x, hist = normal.cg(lambda v: 2.0 * v, rhs, rhs / 2.0, 3)
+    np.testing.assert_array_equal(x, rhs / 2.0)
+    assert np.all(hist == 0.0)
+
+
 def test_lcurve_corner_on_a_known_bend():
     # (log rho, log eta) along a vertical then a horizontal segment: the
     # only bend is at index 6
