@@ -49,6 +49,7 @@ extern "C" {
 #endif
 
 typedef struct spfel_plan_s *spfel_plan;
+typedef struct spfel_normal_s *spfel_normal;
 
 typedef enum {
   SPFEL_OK = 0,
@@ -280,6 +281,76 @@ int spfel_weighted_residual(spfel_plan plan, const void *slices,
                             const void *images, const float *weights,
                             int64_t count, float scale, const float *scale_dev,
                             void *residual, double *loss, void *stream);
+
+/* ---- Regularised merging: the normal equations of Eq. (2) ----
+ * Section II-C: the autocorrelation solves
+ *     (A* D A + lambda I) x = A* D b + lambda x0,
+ * with A the type-2 operator of the plan's convention (REAL: cos, COMPLEX:
+ * exp(+i k.x)), D the per-point weights, x0 the initial guess.  A* D A is a
+ * convolution on the mode grid (the Toeplitz method): its (k, k') entry is
+ * T[k - k'] with T the type-1 transform of the weights on (2N - 1)^3 modes,
+ *   COMPLEX: T[m] = sum_j d_j exp(-i m.x_j),
+ *   REAL:    C[m] = sum_j d_j cos(m.x_j), and A^T D A x = C * even(x),
+ *            even(x)[k] = (x[k] + x[-k]) / 2 (the cos operator only sees the
+ *            even part of x).
+ * Both are spfel_merge_adjoint of the weights (values 1, weights d) on a
+ * plan with n_model = 2N - 1 and the same points; A* D b is
+ * spfel_merge_adjoint of b with weights d on the size-N plan.  One
+ * application is three DFT contractions to L = 2N cells per axis (the
+ * circular convolution then equals the linear one), a pointwise product with
+ * the transformed kernel and three contractions back; conjugate gradients
+ * solve up to 16 systems (one per lambda) at once, sharing every launch.
+ *
+ * An spfel_normal object holds the DFT tables, the transformed kernel and
+ * the CG vectors for up to max_systems systems (all allocated at create;
+ * later calls allocate nothing).  Vectors are N^3 float32 (REAL) or complex64
+ * (COMPLEX) in the model layout; a batch of n systems is n consecutive
+ * vectors.  Calls on one object share its buffers: work on different
+ * streams must not overlap.  Calculations are float32; the step sizes of CG
+ * stay on the device (no host synchronisation). */
+
+/* n_model odd in 3..511, domain SPFEL_REAL or SPFEL_COMPLEX, max_systems
+ * 1..16, on HIP device `device`.  SPFEL_ENOMEM if the buffers (about
+ * 8 (2N)^3 (max_systems + 1) bytes) do not fit. */
+int spfel_normal_create(spfel_normal *out, int n_model, int domain,
+                        int max_systems, int device);
+
+/* Release the object (queued work that uses it must have completed). */
+int spfel_normal_destroy(spfel_normal nm);
+
+/* Set the Toeplitz kernel: psf is (2N - 1)^3 float32 (REAL: C) or complex64
+ * (COMPLEX: T), index (m0 + N - 1, m1 + N - 1, m2 + N - 1) for mode m.
+ * psf may be reused as soon as the stream reaches this call. */
+int spfel_normal_set_psf(spfel_normal nm, const void *psf, void *stream);
+
+/* y[s] = A* D A x[s] + lambdas[s] x[s] for s < n (n <= max_systems);
+ * lambdas: n host floats, finite and >= 0.  x and y are n vectors each and
+ * must not overlap. */
+int spfel_normal_apply(spfel_normal nm, const void *x, int n,
+                       const float *lambdas, void *y, void *stream);
+
+/* `iters` CG steps on system s: (A* D A + lambdas[s]) x = rhs + lambdas[s]
+ * x0, started at x = x0, for s < n.  rhs = A* D b and x0 are one vector
+ * each (shared by all systems); x_out receives n vectors.  residuals (n x
+ * (iters + 1) device floats, or NULL) receives |r_i| per system and step
+ * (i = 0 is the starting residual).  A system whose residual reaches 0 stops
+ * moving. */
+int spfel_normal_solve(spfel_normal nm, const void *rhs, const void *x0,
+                       int n, const float *lambdas, int iters, void *x_out,
+                       float *residuals, void *stream);
+
+/* The L-curve over the n solutions x (as written by spfel_normal_solve for
+ * the same lambdas, which must be uniformly spaced in log lambda):
+ *   rho_s = |D^(1/2) (A x_s - b)|^2 = x_s.(A* D A x_s) - 2 Re x_s.rhs + bdb,
+ *   eta_s = |x_s - x0|^2,
+ * with bdb = b* D b given by the caller; rho_eta (2n device floats) receives
+ * (rho_s, eta_s).  corner (device int32, or NULL) receives the index of the
+ * largest curvature of (log rho, log eta) as functions of log lambda (central
+ * differences, end points excluded; 0 when n < 3). */
+int spfel_normal_lcurve(spfel_normal nm, const void *x, const void *rhs,
+                        const void *x0, int n, const float *lambdas,
+                        double bdb, float *rho_eta, int32_t *corner,
+                        void *stream);
 
 #ifdef __cplusplus
 }

@@ -65,6 +65,12 @@ SIGNATURES = {
     "spfel_scale_columns": (_int, [_vp, _i64, _i64, _vp, _vp, _vp]),
     "spfel_merge_adjoint": (_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _int, _vp]),
     "spfel_weighted_residual": (_int, [_vp, _vp, _vp, _vp, _i64, _flt, _vp, _vp, _vp, _vp]),
+    "spfel_normal_create": (_int, [ctypes.POINTER(_vp), _int, _int, _int, _int]),
+    "spfel_normal_destroy": (_int, [_vp]),
+    "spfel_normal_set_psf": (_int, [_vp, _vp, _vp]),
+    "spfel_normal_apply": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
+    "spfel_normal_solve": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp, _vp, _vp]),
+    "spfel_normal_lcurve": (_int, [_vp, _vp, _vp, _vp, _int, _vp, _dbl, _vp, _vp, _vp]),
 }
 
 _lib = None

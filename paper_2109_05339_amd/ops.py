@@ -407,3 +407,91 @@ def match_bf16(slices_f32: torch.Tensor, images: "ImagesBF16", best_idx: torch.T
     return match(sb, sn, images.b16, images.norm2, best_idx, best_dist, m_offset=m_offset,
                  mode=MATCH_BF16_RESCORE8, slices_f32=s, images_f32=images.x,
                  slice_err=se, image_err=images.err, flags=flags, workspace=workspace)
+
+
+class Normal:
+    """Tikhonov-regularised normal equations of Eq. (2) for an N^3 model,
+    (A* D A + lambda I) x = A* D b + lambda x0, applied as a convolution with
+    the Toeplitz kernel (``set_psf``) and solved by batched conjugate
+    gradients, one system per lambda (up to ``max_systems``)."""
+
+    def __init__(self, n_model: int, domain: int = REAL, max_systems: int = 8, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.n_model = n_model
+        self.domain = domain
+        self.max_systems = max_systems
+        h = ctypes.c_void_p()
+        check(_lib.lib().spfel_normal_create(ctypes.byref(h), n_model, domain, max_systems,
+                                             dev.index))
+        self._h = h
+
+    @property
+    def cdtype(self):
+        return torch.complex64 if self.domain == COMPLEX else torch.float32
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            check(_lib.lib().spfel_normal_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_psf(self, psf: torch.Tensor) -> None:
+        """Toeplitz kernel on (2N-1)^3 modes: ``merge_adjoint`` of the
+        weights on a plan of size 2N-1."""
+        M = 2 * self.n_model - 1
+        _need(psf, "psf", self.cdtype, self.device, (M, M, M))
+        check(_lib.lib().spfel_normal_set_psf(self._h, _p(psf), _stream(self.device)))
+
+    def _lams(self, lambdas):
+        lam = [float(v) for v in lambdas]
+        if not 1 <= len(lam) <= self.max_systems:
+            raise ValueError(f"need 1..{self.max_systems} lambdas, got {len(lam)}")
+        return len(lam), (ctypes.c_float * len(lam))(*lam)
+
+    def _vecs(self, x, n, name):
+        N = self.n_model
+        _need(x, name, self.cdtype, self.device, (n, N, N, N))
+
+    def apply(self, x: torch.Tensor, lambdas) -> torch.Tensor:
+        """(A* D A + lambda_s) x[s] for a batch x of shape (n, N, N, N)."""
+        n, lam = self._lams(lambdas)
+        self._vecs(x, n, "x")
+        y = torch.empty_like(x)
+        check(_lib.lib().spfel_normal_apply(self._h, _p(x), n, lam, _p(y), _stream(self.device)))
+        return y
+
+    def solve(self, rhs: torch.Tensor, x0: torch.Tensor, lambdas, iters: int,
+              residuals: bool = False):
+        """``iters`` CG steps per lambda from x0; rhs = A* D b.  Returns the
+        solutions (n, N, N, N) and, if asked, |r_i| (n, iters + 1)."""
+        n, lam = self._lams(lambdas)
+        N = self.n_model
+        _need(rhs, "rhs", self.cdtype, self.device, (N, N, N))
+        _need(x0, "x0", self.cdtype, self.device, (N, N, N))
+        x = torch.empty((n, N, N, N), dtype=self.cdtype, device=self.device)
+        res = torch.empty((n, iters + 1), dtype=torch.float32, device=self.device) if residuals else None
+        check(_lib.lib().spfel_normal_solve(self._h, _p(rhs), _p(x0), n, lam, iters, _p(x),
+                                            _p(res), _stream(self.device)))
+        return (x, res) if residuals else x
+
+    def lcurve(self, x: torch.Tensor, rhs: torch.Tensor, x0: torch.Tensor, lambdas, bdb: float):
+        """(rho, eta) per solution (n, 2) and the L-curve corner index (a
+        device int32 scalar)."""
+        n, lam = self._lams(lambdas)
+        N = self.n_model
+        self._vecs(x, n, "x")
+        _need(rhs, "rhs", self.cdtype, self.device, (N, N, N))
+        _need(x0, "x0", self.cdtype, self.device, (N, N, N))
+        re = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        corner = torch.empty((), dtype=torch.int32, device=self.device)
+        check(_lib.lib().spfel_normal_lcurve(self._h, _p(x), _p(rhs), _p(x0), n, lam, float(bdb),
+                                             _p(re), _p(corner), _stream(self.device)))
+        return re, corner

@@ -147,3 +147,30 @@ def test_noalloc_rejects_sizes_beyond_its_scratch_before_any_launch():
     assert "scratch" in L.spfel_last_error().decode()
     assert L.spfel_match_noalloc(p, p, p, p, -1, 10, 64, 0, 0, None, None, None, None, p, p,
                                  None, None) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("args", [
+    (8, 0, 4, 0),       # even N
+    (1, 0, 4, 0),       # N < 3
+    (7, 5, 4, 0),       # domain
+    (7, 0, 0, 0),       # no systems
+    (7, 1, 17, 0),      # more than 16 systems
+])
+def test_normal_create_validation(args):
+    h = ctypes.c_void_p()
+    assert spfel.lib().spfel_normal_create(ctypes.byref(h), *args) == _lib.EINVAL
+    assert h.value is None
+    assert spfel.lib().spfel_normal_create(None, 7, 0, 4, 0) == _lib.EINVAL
+    assert spfel.lib().spfel_normal_create(ctypes.byref(h), 513, 0, 4, 0) == _lib.ERANGE
+
+
+def test_normal_calls_reject_dead_handles():
+    L = spfel.lib()
+    bogus = ctypes.c_void_p(0x1000)
+    lam = (ctypes.c_float * 1)(1.0)
+    assert L.spfel_normal_destroy(bogus) == _lib.ESTATE
+    assert L.spfel_normal_set_psf(bogus, 0x2000, None) == _lib.ESTATE
+    assert L.spfel_normal_apply(bogus, 0x2000, 1, lam, 0x3000, None) == _lib.ESTATE
+    assert L.spfel_normal_solve(bogus, 0x2000, 0x2000, 1, lam, 5, 0x3000, None, None) == _lib.ESTATE
+    assert L.spfel_normal_lcurve(bogus, 0x2000, 0x2000, 0x2000, 1, lam, 0.0, 0x3000, None,
+                                 None) == _lib.ESTATE
