@@ -361,7 +361,54 @@ def bench_streaming(args, cfg, dev):
         f"certified {out['certified_fraction']:.4f}")
     if not args.no_extras:
         out["bf16_vs_fp32"] = agreement_subset(plan, model, ref_q, images, bi, chunks, dev)
+        qm = ref_q[bi.long()].contiguous()
+        del plan
+        out["regularised_merge"] = bench_normal(cfg, dev, det, qm, merged, model)
     return out
+
+
+def bench_normal(cfg, dev, det, quats, rhs, x0, n_sys=8, iters=10):
+    """Regularised merging of Eq. (2) at the workload's size: the Toeplitz
+    kernel (type-1 of the unit weights of every image at its matched
+    orientation on 2N - 1 modes), then batched CG over n_sys lambdas on
+    (A* A + lambda I) x = A* b + lambda x0 with A* b the step's merge."""
+    import torch
+    import paper_2109_05339_amd as spfel
+    N = cfg.n_model
+    n_img, P = quats.shape[0], det.shape[0]
+    big = spfel.Plan(2 * N - 1, device=dev)
+    big.set_detector(det)
+    ones = torch.ones((n_img, P), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    tm = Timer(torch, stream)
+    with tm.span("psf"):
+        psf = big.merge_adjoint(quats, None, ones)
+    del big, ones
+    nm = spfel.Normal(N, domain=spfel.REAL, max_systems=n_sys, device=dev)
+    nm.set_psf(psf)
+    lam = (float(n_img) * P / N ** 3 * np.logspace(-3, 0.5, n_sys)).astype(np.float32)
+    nm.solve(rhs, x0, lam, 1)           # warm-up
+    torch.cuda.synchronize()
+    with tm.span("solve0"):
+        nm.solve(rhs, x0, lam, 0)
+    with tm.span("solve"):
+        xs, hist = nm.solve(rhs, x0, lam, iters, residuals=True)
+    with tm.span("lcurve"):
+        re, corner = nm.lcurve(xs, rhs, x0, lam, 0.0)
+    torch.cuda.synchronize()
+    ms0 = tm.ms("solve0")[0]
+    per_it = (tm.ms("solve")[0] - ms0) / iters
+    L = 2 * N
+    # one application per system: REAL input contraction (4 flop per
+    # real x complex term), five complex ones (8 flop), pointwise product
+    work = n_sys * (4.0 * N ** 3 * L + 8.0 * (N ** 2 * L * L + N * L ** 3 + L ** 3 * N
+                                           + L ** 2 * N * N + L * N ** 3) + 6.0 * L ** 3)
+    h = hist.cpu().numpy()
+    return {"systems": n_sys, "N": N, "L": L, "psf_merge_ms": tm.ms("psf")[0],
+            "cg_iteration_ms": per_it, "lcurve_ms": tm.ms("lcurve")[0],
+            "apply_tflops": work / (per_it * 1e-3) / 1e12,
+            "residual_drop": float(np.max(h[:, -1] / h[:, 0])),
+            "corner": int(corner.item())}
 
 
 def agreement_subset(plan, model, ref_q, images, bi_bf16, chunks, dev, n_sub=1024):

@@ -324,15 +324,21 @@ int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
   kernel_transform(n_model, p->nf, kernel_width, p->beta, ph.data());
   const int h = (n_model - 1) / 2;
   std::vector<float2> wp(N * nf), wn(nf * N);
+  // wpos writes the interpolation grid in centred storage (cell l at index
+  // (l + nf/2) mod nf): its phase is that of cell l = index - nf/2.
   for (int ki = 0; ki < n_model; ++ki) {
     const long k = ki - h;
     for (int l = 0; l < p->nf; ++l) {
-      long r = (k * l) % (long)nf;
+      const long nl = (long)nf;
+      long r = (k * l) % nl, rc = (k * ((long)l - nl / 2)) % nl;
       if (r < 0) r += nf;
+      if (rc < 0) rc += nf;
       const double a = 2.0 * M_PI * (double)r / (double)nf;
-      const double c = std::cos(a) / ph[ki], s = std::sin(a) / ph[ki];
-      wp[(size_t)ki * nf + l] = make_float2((float)c, (float)s);
-      wn[(size_t)l * N + ki] = make_float2((float)c, (float)-s);
+      const double ac = 2.0 * M_PI * (double)rc / (double)nf;
+      wp[(size_t)ki * nf + l] =
+          make_float2((float)(std::cos(ac) / ph[ki]), (float)(std::sin(ac) / ph[ki]));
+      wn[(size_t)l * N + ki] =
+          make_float2((float)(std::cos(a) / ph[ki]), (float)(-std::sin(a) / ph[ki]));
     }
   }
   e = hipMemcpy(p->wpos, wp.data(), tab_b, hipMemcpyHostToDevice);

@@ -20,11 +20,12 @@ struct Plan {
   int w = 0;          // kernel width in cells
   int domain = SPFEL_REAL;
   double beta = 0.0;  // kernel shape
-  // Fine grid the interpolation reads: nf^3 float (REAL) or float2 (COMPLEX).
+  // Fine grid the interpolation reads: nf^3 float (REAL) or float2
+  // (COMPLEX), centred storage: cell l at index (l + nf/2) mod nf per axis.
   void *u = nullptr;
   // Separable transform tables, float2, row-major [L][K] for a contraction
   // over L producing K:
-  //   wpos [N][nf]: exp(+2 pi i k l / nf) / psi_hat(k)   (model -> grid)
+  //   wpos [N][nf]: exp(+2 pi i k (l - nf/2) / nf) / psi_hat(k)  (model -> centred grid)
   //   wneg [nf][N]: exp(-2 pi i k l / nf) / psi_hat(k)   (grid -> modes)
   float2 *wpos = nullptr;
   float2 *wneg = nullptr;

@@ -1,6 +1,12 @@
 // Type-2 interpolation (slicing, section II-A): each model image pixel is
 // the ES-kernel-weighted sum of the w^3 fine-grid cells around its rotated
 // Ewald-sphere point, s(x) = sum_{a,b,c} u[l0 + (a,b,c)] psi psi psi.
+//
+// The fine grid is stored centred: cell l (periodic in n_f) sits at index
+// (l + n_f / 2) mod n_f along each axis, so the cells around the origin,
+// where every orientation's points cluster, are contiguous and a support
+// brick wraps only when it reaches |l| ~ n_f / 2, which Ewald-sphere points
+// inside the Nyquist ball never do.
 #include <type_traits>
 
 #include "device_common.h"
@@ -47,6 +53,8 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
   for (int d = 0; d < 3; ++d) {
     const double t = R[3 * d] * q0 + R[3 * d + 1] * q1 + R[3 * d + 2] * q2;
     ok = ok && support_split<W>(t, nf, base[d], frac[d]);
+    base[d] += nf >> 1;   // centred storage
+    base[d] -= base[d] >= nf ? nf : 0;
   }
   if (!ok) {
     const float nan = __uint_as_float(0x7fc00000u);
@@ -212,10 +220,10 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
   if (use_lds && threadIdx.x < 64) {
     // fine-grid offsets of every brick plane, row and column, wrapped once
     // per block (n_f <= 1022, so n_f^3 cells index in 32 bits)
-    const int t = threadIdx.x;
-    if (t < e0) wrap[0][t] = wrap_mod(mn[0] + t, nf) * nf * nf;
-    if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t, nf) * nf;
-    if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t, nf);
+    const int t = threadIdx.x, half = nf >> 1;
+    if (t < e0) wrap[0][t] = wrap_mod(mn[0] + t + half, nf) * nf * nf;
+    if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t + half, nf) * nf;
+    if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t + half, nf);
     if (choose) {
       // candidate c = 4 pe + d: p2 = p4 + pe, s0 = e1 p2 + d, so the origin
       // address is row * (p4 + pe) + d * x0 + x2 with row = x0 e1 + x1
@@ -380,9 +388,9 @@ __global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
     int g0[W], g1[W], g2[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) {
-      g0[a] = wrap_mod(l0[0] + a, nf);
-      g1[a] = wrap_mod(l0[1] + a, nf);
-      g2[a] = wrap_mod(l0[2] + a, nf);
+      g0[a] = wrap_mod(l0[0] + a + (nf >> 1), nf);
+      g1[a] = wrap_mod(l0[1] + a + (nf >> 1), nf);
+      g2[a] = wrap_mod(l0[2] + a + (nf >> 1), nf);
     }
 #pragma unroll
     for (int a = 0; a < W; ++a) {

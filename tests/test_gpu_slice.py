@@ -171,6 +171,30 @@ def test_registered_detector_tiles_are_bitwise_equal_to_generic_path(domain):
     np.testing.assert_array_equal(host(an), host(bn))
 
 
+@pytest.mark.parametrize("M", [1, 2, 33, 70])
+def test_registered_detector_orientation_groups_ragged_and_nonfinite(M):
+    """Orientations are walked in groups of 32 per block: group sizes 1, 2,
+    32 + 1 and 2 x 32 + 6 over a ragged detector (400 points: one full and
+    one partial tile), with a zero and a NaN quaternion inside a group, equal
+    the per-point path bit for bit."""
+    N = 33
+    det = detector(20)
+    q = synth.quaternions(synth.config(1), "ref_quats", M)
+    if M > 2:
+        q[M // 2] = 0.0
+        q[M - 2] = [np.nan, 0, 0, 0]
+    plan = make_plan(N)
+    plan.set_model(gpu(model(1)))
+    plan.set_detector(gpu(det))
+    a = host(plan.slice(gpu(q))[0])
+    b = host(plan.slice(gpu(q), gpu(det))[0])
+    np.testing.assert_array_equal(a, b)
+    bad = [M // 2, M - 2] if M > 2 else []
+    assert np.all(np.isnan(a[bad]))
+    good = np.setdiff1d(np.arange(M), bad)
+    assert rel(a[good], oracle_slices(model(1), q[good], det, real=True)) <= TOL
+
+
 @pytest.mark.parametrize("cid,rows", [(2, 4), (5, 2)])
 def test_registered_detector_large_shapes_against_oracle(cid, rows):
     cfg = synth.config(cid)
