@@ -13,7 +13,9 @@ passage of the SpiniFEL paper (arXiv 2109.05339) it follows:
   Euclidean distance, nearest model image wins;
 * merging, section II-C, Eq. (1)-(2): the type-1 NUFFT A* (with weights D)
   as the adjoint of slicing, and the regularised normal equations of
-  Eq. (2) with their Toeplitz form, conjugate gradients and the L-curve.
+  Eq. (2) with their Toeplitz form, conjugate gradients and the L-curve;
+* phasing, section II-D: error reduction, hybrid input-output and
+  shrinkwrap between the density and its measured Fourier amplitudes.
 
 The paper fixes no NUFFT internals; it names the ES-kernel library of its
 reference [barnett2019parallel].  The readings used (kernel, width, shape
@@ -24,4 +26,4 @@ Parity status: every function below is pinned by a CPU test (closed forms,
 brute force, library routines or invariants), except where its docstring
 says "parity unpinned".
 """
-from . import es, geometry, nudft, nufft, match, grad, normal  # noqa: F401
+from . import es, geometry, nudft, nufft, match, grad, normal, phasing  # noqa: F401
