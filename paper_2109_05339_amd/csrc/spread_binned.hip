@@ -277,10 +277,12 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
   constexpr int kA = CPLX ? 2 : 1;
   // per wavefront and batch point: the brick-shifted rows y psi0 (re[, im])
   // and psi2 over the 16 brick cells of axes 0 and 2, and psi1 (its w
-  // values); row kPer is all zero (the pad of a partial group of four)
+  // values); row kPer is all zero (the pad of a partial group of four).
+  // The psi1 rows have an odd pitch (9), so the lanes writing their points'
+  // rows fall in distinct banks.
   __shared__ __attribute__((aligned(16))) float rowA[4][kA][kPer + 1][kBrick];
   __shared__ __attribute__((aligned(16))) float rowB[4][kPer + 1][kBrick];
-  __shared__ __attribute__((aligned(16))) float rowC[4][kPer + 1][8];
+  __shared__ __attribute__((aligned(16))) float rowC[4][kPer + 1][9];
   if ((int)blockIdx.x >= *nsub) return;   // block-uniform
   const int4 sp = sub[blockIdx.x];
   const int bin = sp.x, start = sp.y, end = sp.z;
@@ -375,9 +377,13 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
   if constexpr (Bo > 12) run(std::integral_constant<int, (Bo > 12 ? 12 : 0)>{});
   // Sum the four wavefronts' bricks in LDS (wave 0 stores, then waves 1-3
   // add in order), then flush.  Result lane layout: lane l holds
-  // accumulator plane pl, rows 4 (l / 16) + j (axis 0), column l % 16 (axis 2).
+  // accumulator plane pl, rows 4 (l / 16) + j (axis 0), column l % 16 (axis
+  // 2).  Each axis-0 slab of 256 cells is padded by 4 floats, so the four
+  // 16-lane groups of a wavefront (slabs 4 apart) fall in distinct banks.
   __syncthreads();
-  float *red = &rowA[0][0][0][0];   // kA x 4,096 floats fit in rowA
+  float *red = &rowA[0][0][0][0];   // kA x 16 x 260 floats fill rowA exactly
+  static_assert(sizeof(rowA) >= sizeof(float) * kA * kBrick * (kBrick * kBrick + 4),
+                "reduction buffer");
   for (int wv = 0; wv < 4; ++wv) {
     if (wave == wv) {
 #pragma unroll
@@ -385,7 +391,7 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i0 = 4 * kq + j;
-          const int c = (i0 * kBrick + pl) * kBrick + r;
+          const int c = (i0 * kBrick + pl) * kBrick + r + 4 * i0;
           if (wv == 0) {
             red[kA * c] = accr[pl][j];
             if (CPLX) red[kA * c + 1] = acci[CPLX ? pl : 0][j];
@@ -406,9 +412,9 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
     g1 %= nf;
     g2 %= nf;
     const int64_t cell = ((int64_t)g0 * nf + g1) * nf + g2;
-    const float vr = red[kA * c];
+    const float vr = red[kA * (c + 4 * i0)];
     if (CPLX) {
-      const float vi = red[kA * c + 1];
+      const float vi = red[kA * (c + 4 * i0) + 1];
       if (vr != 0.f) unsafeAtomicAdd(grid + 2 * cell, vr);
       if (vi != 0.f) unsafeAtomicAdd(grid + 2 * cell + 1, vi);
     } else {
