@@ -364,7 +364,44 @@ def bench_streaming(args, cfg, dev):
         qm = ref_q[bi.long()].contiguous()
         del plan
         out["regularised_merge"] = bench_normal(cfg, dev, det, qm, merged, model)
+        out["phasing"] = bench_phasing(cfg, dev)
     return out
+
+
+def bench_phasing(cfg, dev, iters=20):
+    """Phasing at the workload's grid size: HIO iterations (two N^3 DFTs,
+    the amplitude and support projections) and one shrinkwrap, on a seeded
+    positive density in a ball (amplitudes from torch's FFT of it: input
+    preparation only)."""
+    import torch
+    import paper_2109_05339_amd as spfel
+    N = cfg.n_model
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(cfg.seed_id) * 7919)
+    c = torch.arange(N, device=dev, dtype=torch.float32) - N // 2
+    R2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+    sup = (R2 <= (N / 4) ** 2)
+    rho = torch.rand((N, N, N), generator=g, device=dev) * sup
+    amp = torch.fft.fftn(rho.double()).abs().float().contiguous()
+    x = (torch.rand((N, N, N), generator=g, device=dev) * sup).contiguous()
+    s8 = sup.to(torch.uint8).contiguous()
+    p = spfel.Phase(N, device=dev)
+    p.iterate(x, amp, s8, 1)                   # warm-up
+    stream = torch.cuda.current_stream(dev)
+    tm = Timer(torch, stream)
+    with tm.span("hio"):
+        err = p.iterate(x, amp, s8, iters, errors=True)
+    with tm.span("shrinkwrap"):
+        p.shrinkwrap(x, 2.0, 0.1)
+    torch.cuda.synchronize()
+    ms = tm.ms("hio")[0] / iters
+    # two 3D DFTs per iteration: 3 contractions of N^4 complex MACs each
+    # (the first real x complex), 8 flop per complex MAC
+    flop = 2 * 3 * 8.0 * N ** 4
+    e = err.cpu().numpy()
+    return {"N": N, "iteration_ms": ms, "shrinkwrap_ms": tm.ms("shrinkwrap")[0],
+            "dft_tflops": flop / (ms * 1e-3) / 1e12, "error_first": float(e[0]),
+            "error_last": float(e[-1])}
 
 
 def bench_normal(cfg, dev, det, quats, rhs, x0, n_sys=8, iters=10):

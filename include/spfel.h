@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct spfel_plan_s *spfel_plan;
 typedef struct spfel_normal_s *spfel_normal;
+typedef struct spfel_phase_s *spfel_phase;
 
 typedef enum {
   SPFEL_OK = 0,
@@ -65,6 +66,7 @@ enum { SPFEL_REAL = 0, SPFEL_COMPLEX = 1 };
 enum { SPFEL_F32 = 0, SPFEL_BF16 = 1 };
 enum { SPFEL_MATCH_FP32 = 0, SPFEL_MATCH_BF16_RESCORE8 = 1 };
 enum { SPFEL_MERGE_ACCUMULATE = 1, SPFEL_MERGE_DEFER = 2 };
+enum { SPFEL_PHASE_ER = 0, SPFEL_PHASE_HIO = 1 };
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int spfel_version(void);
@@ -351,6 +353,49 @@ int spfel_normal_lcurve(spfel_normal nm, const void *x, const void *rhs,
                         const void *x0, int n, const float *lambdas,
                         double bdb, float *rho_eta, int32_t *corner,
                         void *stream);
+
+/* ---- Phasing (section II-D) ----
+ * The density rho (real, N^3 float32, C order) and its 3D DFT
+ * F[k] = sum_r rho[r] exp(-2 pi i k.r / N) (numpy's convention and standard
+ * index order for k) are driven between the real-space constraints and the
+ * measured amplitudes:
+ *   reciprocal space: where measured[k] (all k if measured is NULL),
+ *     F[k] <- amp[k] F[k] / |F[k]| (amp[k] where F[k] = 0); elsewhere F[k]
+ *     is kept; rho' = Re IFFT(F);
+ *   real space: where the constraint holds (support[r] != 0, and rho'[r]
+ *     >= 0 when positivity is set) rho <- rho'; elsewhere rho <- 0 (error
+ *     reduction, ER) or rho - beta rho' (hybrid input-output, HIO);
+ *   error of an iteration: sum over measured k of (|F| - amp)^2 / sum of
+ *     amp^2, from the transform of the iterate the iteration starts from.
+ * Shrinkwrap replaces the support by the cells where the periodic Gaussian
+ * blur (standard deviation sigma cells, unit sum, separable circular
+ * convolution) of |rho| reaches tau times its maximum.
+ * The transforms are separable DFT contractions (float32).  An spfel_phase
+ * object holds the tables and intermediates for one N (about 28 N^3 bytes,
+ * allocated at create; later calls allocate nothing); calls on one object
+ * share them, so work on different streams must not overlap. */
+
+/* n in 2..1024 cells per axis, on HIP device `device`. */
+int spfel_phase_create(spfel_phase *out, int n, int device);
+
+/* Release the object (queued work that uses it must have completed). */
+int spfel_phase_destroy(spfel_phase ph);
+
+/* n_iter iterations of mode SPFEL_PHASE_ER or SPFEL_PHASE_HIO (beta used by
+ * HIO) on rho in place.  amp: N^3 float32 amplitudes; measured, support:
+ * N^3 bytes (0 / nonzero; measured may be NULL); err: n_iter device
+ * floats or NULL, receives each iteration's error. */
+int spfel_phase_iterate(spfel_phase ph, float *rho, const float *amp,
+                        const uint8_t *measured, const uint8_t *support,
+                        int n_iter, int mode, float beta, int positivity,
+                        float *err, void *stream);
+
+/* Shrinkwrap: support (N^3 bytes) <- blur(|rho|, sigma) >= tau max, sigma
+ * > 0, tau in [0, 1]; blurred (N^3 float32, or NULL) receives the blurred
+ * |rho|. */
+int spfel_phase_shrinkwrap(spfel_phase ph, const float *rho, float sigma,
+                           float tau, uint8_t *support, float *blurred,
+                           void *stream);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,10 @@ SIGNATURES = {
     "spfel_normal_apply": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
     "spfel_normal_solve": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp, _vp, _vp]),
     "spfel_normal_lcurve": (_int, [_vp, _vp, _vp, _vp, _int, _vp, _dbl, _vp, _vp, _vp]),
+    "spfel_phase_create": (_int, [ctypes.POINTER(_vp), _int, _int]),
+    "spfel_phase_destroy": (_int, [_vp]),
+    "spfel_phase_iterate": (_int, [_vp, _vp, _vp, _vp, _vp, _int, _int, _flt, _int, _vp, _vp]),
+    "spfel_phase_shrinkwrap": (_int, [_vp, _vp, _flt, _flt, _vp, _vp, _vp]),
 }
 
 _lib = None

@@ -18,7 +18,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libspfel.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "transform.hip", "interp.hip", "spread.hip", "spread_binned.hip", "match.hip", "centre.hip", "residual.hip", "noalloc.hip", "normal.hip"]
+SOURCES = ["api.cpp", "transform.hip", "interp.hip", "spread.hip", "spread_binned.hip", "match.hip", "centre.hip", "residual.hip", "noalloc.hip", "normal.hip", "phasing.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -19,6 +19,7 @@ REAL, COMPLEX = 0, 1
 F32, BF16 = 0, 1
 MATCH_FP32, MATCH_BF16_RESCORE8 = 0, 1
 MERGE_ACCUMULATE, MERGE_DEFER = 1, 2
+PHASE_ER, PHASE_HIO = 0, 1
 
 
 def _stream(dev: torch.device) -> int:
@@ -495,3 +496,65 @@ class Normal:
         check(_lib.lib().spfel_normal_lcurve(self._h, _p(x), _p(rhs), _p(x0), n, lam, float(bdb),
                                              _p(re), _p(corner), _stream(self.device)))
         return re, corner
+
+
+class Phase:
+    """Phasing on an N^3 grid (section II-D): ER and HIO iterations between
+    the support/positivity constraints and the measured Fourier amplitudes,
+    and shrinkwrap support updates."""
+
+    def __init__(self, n: int, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.n = n
+        h = ctypes.c_void_p()
+        check(_lib.lib().spfel_phase_create(ctypes.byref(h), n, dev.index))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            check(_lib.lib().spfel_phase_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _grid(self, t, name, dtype):
+        n = self.n
+        _need(t, name, dtype, self.device, (n, n, n))
+
+    def iterate(self, rho: torch.Tensor, amp: torch.Tensor, support: torch.Tensor, n_iter: int,
+                mode: int = PHASE_HIO, beta: float = 0.9, positivity: bool = True,
+                measured: Optional[torch.Tensor] = None, errors: bool = False):
+        """n_iter iterations on rho (N^3 float32) in place; returns the
+        per-iteration errors (device float32) if asked."""
+        self._grid(rho, "rho", torch.float32)
+        self._grid(amp, "amp", torch.float32)
+        self._grid(support, "support", torch.uint8)
+        if measured is not None:
+            self._grid(measured, "measured", torch.uint8)
+        err = torch.empty((n_iter,), dtype=torch.float32, device=self.device) if errors else None
+        check(_lib.lib().spfel_phase_iterate(self._h, _p(rho), _p(amp), _p(measured), _p(support),
+                                             n_iter, mode, float(beta), 1 if positivity else 0,
+                                             _p(err), _stream(self.device)))
+        return err
+
+    def shrinkwrap(self, rho: torch.Tensor, sigma: float, tau: float,
+                   support: Optional[torch.Tensor] = None, blurred: bool = False):
+        """New support (N^3 uint8) from the blurred |rho|; with blurred=True
+        also returns the blur."""
+        self._grid(rho, "rho", torch.float32)
+        n = self.n
+        if support is None:
+            support = torch.empty((n, n, n), dtype=torch.uint8, device=self.device)
+        else:
+            self._grid(support, "support", torch.uint8)
+        b = torch.empty((n, n, n), dtype=torch.float32, device=self.device) if blurred else None
+        check(_lib.lib().spfel_phase_shrinkwrap(self._h, _p(rho), float(sigma), float(tau),
+                                                _p(support), _p(b), _stream(self.device)))
+        return (support, b) if blurred else support

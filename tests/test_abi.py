@@ -174,3 +174,17 @@ def test_normal_calls_reject_dead_handles():
     assert L.spfel_normal_solve(bogus, 0x2000, 0x2000, 1, lam, 5, 0x3000, None, None) == _lib.ESTATE
     assert L.spfel_normal_lcurve(bogus, 0x2000, 0x2000, 0x2000, 1, lam, 0.0, 0x3000, None,
                                  None) == _lib.ESTATE
+
+
+def test_phase_create_validation_and_dead_handles():
+    L = spfel.lib()
+    h = ctypes.c_void_p()
+    assert L.spfel_phase_create(ctypes.byref(h), 1, 0) == _lib.EINVAL
+    assert L.spfel_phase_create(ctypes.byref(h), 1025, 0) == _lib.ERANGE
+    assert L.spfel_phase_create(None, 16, 0) == _lib.EINVAL
+    assert h.value is None
+    bogus = ctypes.c_void_p(0x1000)
+    assert L.spfel_phase_destroy(bogus) == _lib.ESTATE
+    assert L.spfel_phase_iterate(bogus, 0x2000, 0x2000, None, 0x2000, 1, 0, 0.9, 1, None,
+                                 None) == _lib.ESTATE
+    assert L.spfel_phase_shrinkwrap(bogus, 0x2000, 1.0, 0.1, 0x2000, None, None) == _lib.ESTATE
