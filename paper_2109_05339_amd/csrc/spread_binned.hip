@@ -337,28 +337,46 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
       }
       __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wavefront's rows are written
       __builtin_amdgcn_wave_barrier();
-      for (int p0 = 0; p0 < cnt; p0 += 4) {
+      // Matrix steps of four points, software-pipelined over two register
+      // sets: the next step's rows are read from LDS before this step's
+      // matrix instructions issue (the scheduling barriers keep them there).
+      const int ucnt = __builtin_amdgcn_readfirstlane(cnt);
+      auto fetch = [&](int p0, float &fa, float &fai, float &fb, float (&fc)[W]) {
         const int p = p0 + kq;
-        const int pp = p < cnt ? p : kPer;
-        const float a = rowA[wave][0][pp][r];
-        const float ai = CPLX ? rowA[wave][kA - 1][pp][r] : 0.f;
-        const float bv = rowB[wave][pp][r];
-        float c[W];
+        const int pp = p < ucnt ? p : kPer;   // past the end: the zero row
+        fa = rowA[wave][0][pp][r];
+        fai = CPLX ? rowA[wave][kA - 1][pp][r] : 0.f;
+        fb = rowB[wave][pp][r];
 #pragma unroll
-        for (int d = 0; d < W; ++d) c[d] = rowC[wave][pp][d];
-        float ar[W], aim[W];
-#pragma unroll
-        for (int d = 0; d < W; ++d) {
-          ar[d] = a * c[d];
-          if (CPLX) aim[d] = ai * c[d];
-        }
+        for (int d = 0; d < W; ++d) fc[d] = rowC[wave][pp][d];
+      };
+      auto step = [&](float a, float ai, float bv, const float (&c)[W]) {
 #pragma unroll
         for (int d = 0; d < W; ++d) {
-          accr[V + d] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[d], bv, accr[V + d], 0, 0, 0);
+          accr[V + d] = __builtin_amdgcn_mfma_f32_16x16x4f32(a * c[d], bv, accr[V + d], 0, 0, 0);
           if (CPLX)
-            acci[CPLX ? V + d : 0] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(aim[d], bv, acci[CPLX ? V + d : 0], 0, 0, 0);
+            acci[CPLX ? V + d : 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                ai * c[d], bv, acci[CPLX ? V + d : 0], 0, 0, 0);
         }
+      };
+      float xa0, xi0, xb0, xc0[W], xa1, xi1, xb1, xc1[W];
+      fetch(0, xa0, xi0, xb0, xc0);
+      // The first step's values pass through an empty asm statement: with
+      // only loads flowing into the loop-carried set the compiler would fold
+      // them into one load at the use, undoing the pipelining.
+      __asm__ __volatile__("" : "+v"(xa0), "+v"(xi0), "+v"(xb0));
+#pragma unroll
+      for (int d = 0; d < W; ++d) __asm__ __volatile__("" : "+v"(xc0[d]));
+      for (int p0 = 0; p0 < ucnt; p0 += 8) {
+        fetch(p0 + 4, xa1, xi1, xb1, xc1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(xa0, xi0, xb0, xc0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (p0 + 4 >= ucnt) break;   // wavefront-uniform
+        fetch(p0 + 8, xa0, xi0, xb0, xc0);
+        __builtin_amdgcn_sched_barrier(0);
+        step(xa1, xi1, xb1, xc1);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   };
