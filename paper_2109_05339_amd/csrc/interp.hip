@@ -138,10 +138,10 @@ __global__ __launch_bounds__(256) void interp_gather_kernel(
 // stages in LDS with coalesced row reads; the w^3 gather then reads LDS
 // instead of L1/L2.  A brick larger than the LDS budget (possible only for
 // unusually spread tiles) makes the block gather from global memory.
-// LDS budget of a brick: 32 KB of float (4 blocks per CU) or 64 KB of
-// float2 cells.
+// LDS budget of a brick: 29 KB of float (5 blocks per CU, the kernel then
+// fits in 81 registers) or 64 KB of float2 cells.
 template <bool CPLX>
-constexpr int brick_bytes() { return CPLX ? 65536 : 32768; }
+constexpr int brick_bytes() { return CPLX ? 65536 : 29696; }
 
 // The LDS serves 128 bytes per cycle: a wavefront's reads of T cells go
 // through in passes of 128 / sizeof(T) lanes, and bank conflicts arise
@@ -155,7 +155,7 @@ __device__ inline int wrap_mod(int v, int n) {
 }
 
 template <int W, bool CPLX>
-__global__ __launch_bounds__(kTile, 4) void interp_tiled_kernel(
+__global__ __launch_bounds__(kTile, CPLX ? 4 : 5) void interp_tiled_kernel(
     const void *__restrict__ u_, int nf, float beta, const double *__restrict__ rot, int64_t M,
     const float *__restrict__ dets, const int32_t *__restrict__ perm, int64_t P, int tiles,
     void *__restrict__ out_) {
