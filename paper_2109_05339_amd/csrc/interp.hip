@@ -147,7 +147,7 @@ constexpr int brick_bytes() { return CPLX ? 65536 : 29696; }
 // through in passes of 128 / sizeof(T) lanes, and bank conflicts arise
 // among the lanes of one pass.  kLayouts candidate brick layouts are scored
 // per block.
-constexpr int kLayouts = 16;
+constexpr int kLayouts = 8;
 
 __device__ inline int wrap_mod(int v, int n) {
   v %= n;
@@ -211,12 +211,14 @@ __global__ __launch_bounds__(kTile, CPLX ? 4 : 5) void interp_tiled_kernel(
   // slot back: a lane that finds another address there shares its banks
   // with a different cell in its pass.  The candidate with the fewest such
   // lanes wins (ties: the first); the other wavefronts' patches lie next to
-  // the first's, under the same rotation, and share its choice.
+  // the first's, under the same rotation, and share its choice.  Eight
+  // candidates (row paddings 0-3, plane offsets 0 and 2) choose as well as
+  // sixteen (offsets 0-3) at half the probe's cost.
   constexpr int kVec = 16 / (int)sizeof(T);
   const int nseg = (e2 + kVec - 1) / kVec;
   const int p4 = nseg * kVec;
   const bool use_lds = any && e0 <= 64 && e1 <= 64 && e2 <= 64 && e0 * e1 * p4 <= kCap;
-  const bool choose = use_lds && e0 * (e1 * (p4 + 3) + 3) <= kCap;
+  const bool choose = use_lds && e0 * (e1 * (p4 + 3) + 2) <= kCap;
   if (use_lds && threadIdx.x < 64) {
     // fine-grid offsets of every brick plane, row and column, wrapped once
     // per block (n_f <= 1022, so n_f^3 cells index in 32 bits)
@@ -225,8 +227,9 @@ __global__ __launch_bounds__(kTile, CPLX ? 4 : 5) void interp_tiled_kernel(
     if (t < e1) wrap[1][t] = wrap_mod(mn[1] + t + half, nf) * nf;
     if (t < e2) wrap[2][t] = wrap_mod(mn[2] + t + half, nf);
     if (choose) {
-      // candidate c = 4 pe + d: p2 = p4 + pe, s0 = e1 p2 + d, so the origin
-      // address is row * (p4 + pe) + d * x0 + x2 with row = x0 e1 + x1
+      // candidate c = 2 pe + d / 2: p2 = p4 + pe, s0 = e1 p2 + d (d = 0, 2),
+      // so the origin address is row * (p4 + pe) + d * x0 + x2 with
+      // row = x0 e1 + x1
       const int x0 = l0[0] - mn[0], row = x0 * e1 + (l0[1] - mn[1]);
       // a table per candidate and pass of kPass lanes, one slot per bank
       // group (cell address mod kPass) plus one for invalid lanes
@@ -238,12 +241,12 @@ __global__ __launch_bounds__(kTile, CPLX ? 4 : 5) void interp_tiled_kernel(
       for (int pe = 0; pe < 4; ++pe) {
         int a = a_pe;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int c = 4 * pe + d;
+        for (int dd = 0; dd < 2; ++dd) {
+          const int c = 2 * pe + dd;
           addr[c] = a;
           slot[c] = kPasses * c * (kPass + 1) + (valid ? (a & (kPass - 1)) : kPass);
           tab[slot[c]] = a;
-          a += x0;
+          a += 2 * x0;
         }
         a_pe += row;
       }
@@ -261,15 +264,15 @@ __global__ __launch_bounds__(kTile, CPLX ? 4 : 5) void interp_tiled_kernel(
         const int n = __popcll(__ballot(valid && got[c] != addr[c]));
         best_key = min(best_key, (n << 4) | c);
       }
-      if (t == 0) layout[0] = best_key & 15;
+      if (t == 0) layout[0] = best_key & 15;   // c < 8
     }
   }
   if (use_lds) __syncthreads();
   int p2 = p4, s0 = e1 * p4;
   if (choose) {
     const int best = layout[0];
-    p2 = p4 + (best >> 2);
-    s0 = e1 * p2 + (best & 3);
+    p2 = p4 + (best >> 1);
+    s0 = e1 * p2 + 2 * (best & 1);
   }
   const T *u = static_cast<const T *>(u_);
   if (use_lds) {
