@@ -149,9 +149,15 @@ constexpr int brick_bytes() { return CPLX ? 65536 : 29696; }
 // per block.
 constexpr int kLayouts = 8;
 
+// v mod n in [0, n); the common case (v within one period of the range)
+// takes one conditional add, the integer division only the rest.
 __device__ inline int wrap_mod(int v, int n) {
-  v %= n;
-  return v < 0 ? v + n : v;
+  v += v < 0 ? n : 0;
+  if ((unsigned)v >= (unsigned)n) {
+    v %= n;
+    v += v < 0 ? n : 0;
+  }
+  return v;
 }
 
 template <int W, bool CPLX>

@@ -46,9 +46,15 @@ __device__ inline bool point_support(const double *__restrict__ Rs, const float 
     if (!(fabs(t) < 1e8)) return false;
     const double c = ceil(t - 0.5 * W);
     frac[d] = (float)(t - c);
-    long long ci = (long long)c % nf;
-    if (ci < 0) ci += nf;
-    L[d] = (int)ci;
+    // c mod nf (|c| < 1e8 + W fits an int); points within one period of
+    // the grid take the conditional add only
+    int ci = (int)c;
+    ci += ci < 0 ? nf : 0;
+    if ((unsigned)ci >= (unsigned)nf) {
+      ci %= nf;
+      ci += ci < 0 ? nf : 0;
+    }
+    L[d] = ci;
   }
   return true;
 }
@@ -425,10 +431,12 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
   const int lo0 = bb0 * Bo, lo1 = bb1 * Bo, lo2 = bb2 * Bo;
   for (int c = tid; c < kBrick * kBrick * kBrick; c += 256) {
     const int i2 = c & 15, i1 = (c >> 4) & 15, i0 = c >> 8;
+    // lo < nf and i < 16: one subtraction wraps unless the grid is
+    // smaller than a brick
     int g0 = lo0 + i0, g1 = lo1 + i1, g2 = lo2 + i2;
-    g0 %= nf;
-    g1 %= nf;
-    g2 %= nf;
+    if (g0 >= nf) g0 = nf >= kBrick ? g0 - nf : g0 % nf;
+    if (g1 >= nf) g1 = nf >= kBrick ? g1 - nf : g1 % nf;
+    if (g2 >= nf) g2 = nf >= kBrick ? g2 - nf : g2 % nf;
     const int64_t cell = ((int64_t)g0 * nf + g1) * nf + g2;
     const float vr = red[kA * (c + 4 * i0)];
     if (CPLX) {
