@@ -211,3 +211,32 @@ def test_state_and_argument_errors():
     torch.cuda.synchronize()
     nm.close()
     assert L.spfel_normal_set_psf(nm._h, v.data_ptr(), None) == _lib.ESTATE
+
+
+def test_operator_at_the_workload_size_on_sampled_outputs():
+    """N = 129 (L = 258), 8 systems as the bench runs them, REAL domain:
+    sampled outputs against direct sums over the kernel (each O(N^3)), and
+    the operator's symmetry <u, H v> = <H u, v> over the whole grid."""
+    N, M = 129, 257
+    g = np.random.default_rng(21)
+    C = g.standard_normal((M, M, M)).astype(np.float32)
+    C = 0.5 * (C + C[::-1, ::-1, ::-1])                       # cosine kernel: even
+    nm = spfel.Normal(N, max_systems=8, device=DEV)
+    nm.set_psf(gpu(C))
+    v = g.standard_normal((8, N, N, N)).astype(np.float32)
+    lams = [0.0, 0.5, 1.0, 2.0, 0.0, 3.0, 0.25, 1.5]
+    y = host(nm.apply(gpu(v), lams))
+    C64 = C.astype(np.float64)
+    for s in (0, 5):
+        ve = normal.even_part(v[s].astype(np.float64))
+        for k in g.integers(0, N, size=(12, 3)):
+            # y[k] = sum_k' C[k - k'] even(v)[k'] + lambda v[k]
+            win = C64[k[0]:k[0] + N, k[1]:k[1] + N, k[2]:k[2] + N][::-1, ::-1, ::-1]
+            want = float(np.sum(win * ve)) + lams[s] * float(v[s][tuple(k)])
+            scale = np.sqrt(np.sum(win * win) * np.sum(ve * ve))
+            assert abs(y[s][tuple(k)] - want) <= 1e-5 * scale
+    u = g.standard_normal((1, N, N, N)).astype(np.float32)
+    Hu = host(nm.apply(gpu(u), [0.0]))[0].astype(np.float64)
+    Hv = y[0].astype(np.float64)
+    a, b = float(np.sum(u[0] * Hv)), float(np.sum(Hu * v[0]))
+    assert abs(a - b) <= 1e-4 * np.linalg.norm(Hu) * np.linalg.norm(v[0])

@@ -165,3 +165,24 @@ def test_argument_errors():
     torch.cuda.synchronize()
     p.close()
     assert L.spfel_phase_destroy(p._h) == _lib.ESTATE
+
+
+def test_hio_step_at_the_workload_size():
+    """N = 129, as the bench runs it: one HIO step with positivity off and a
+    beam stop against the oracle over the whole grid."""
+    N = 129
+    g = np.random.default_rng(12)
+    c = np.arange(N) - N // 2
+    R2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+    sup = R2 <= (N // 4) ** 2
+    rho = g.random((N, N, N)) * sup
+    A = np.abs(np.fft.fftn(rho)).astype(np.float32)
+    x = (g.random((N, N, N)) * sup).astype(np.float32)
+    meas = beam_stop(N, 3.0)
+    p = spfel.Phase(N, device=DEV)
+    r = gpu(x)
+    err = p.iterate(r, gpu(A), gpu(sup, torch.uint8), 1, mode=spfel.PHASE_HIO, beta=0.9,
+                    positivity=False, measured=gpu(meas, torch.uint8), errors=True)
+    want, we = ph.hio_step(f32(x), f32(A), sup, 0.9, meas, False)
+    assert rel(host(r), want) <= 1e-5
+    assert abs(float(host(err)[0]) - we) <= 1e-5 * we
