@@ -348,7 +348,8 @@ int spfel_normal_solve(spfel_normal nm, const void *rhs, const void *x0,
  * with bdb = b* D b given by the caller; rho_eta (2n device floats) receives
  * (rho_s, eta_s).  corner (device int32, or NULL) receives the index of the
  * largest curvature of (log rho, log eta) as functions of log lambda (central
- * differences, end points excluded; 0 when n < 3). */
+ * differences, end points excluded; 0 when n < 3).  With n >= 3 every
+ * lambda must be > 0. */
 int spfel_normal_lcurve(spfel_normal nm, const void *x, const void *rhs,
                         const void *x0, int n, const float *lambdas,
                         double bdb, float *rho_eta, int32_t *corner,

@@ -397,6 +397,11 @@ int spfel_normal_set_psf(spfel_normal h, const void *psf, void *stream) {
   return SPFEL_OK;
 }
 
+// Vectors are float32 (REAL) or complex64 (COMPLEX) arrays.
+static bool vec_aligned(const Normal *p, const void *v) {
+  return (reinterpret_cast<uintptr_t>(v) & (p->domain == SPFEL_COMPLEX ? 7 : 3)) == 0;
+}
+
 static int check_lambdas(const Normal *p, int n, const float *lambdas, Lambdas &lam,
                          const char *who) {
   if (n < 1 || n > p->max_sys) return fail(SPFEL_EINVAL, std::string(who) + ": n out of 1..max_systems");
@@ -420,6 +425,7 @@ int spfel_normal_apply(spfel_normal h, const void *x, int n, const float *lambda
   int rc = check_lambdas(p, n, lambdas, lam, "normal_apply");
   if (rc != SPFEL_OK) return rc;
   if (!x || !y) return fail(SPFEL_EINVAL, "normal_apply: NULL pointer");
+  if (!vec_aligned(p, x) || !vec_aligned(p, y)) return fail(SPFEL_EINVAL, "normal_apply: misaligned vector");
   hipError_t e = normal_apply(*p, x, n, &lam, y, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SPFEL_OK : hip_fail(e, "normal_apply: launch");
 }
@@ -435,6 +441,9 @@ int spfel_normal_solve(spfel_normal h, const void *rhs, const void *x0, int n,
   int rc = check_lambdas(p, n, lambdas, lam, "normal_solve");
   if (rc != SPFEL_OK) return rc;
   if (!rhs || !x0 || !x_out) return fail(SPFEL_EINVAL, "normal_solve: NULL pointer");
+  if (!vec_aligned(p, rhs) || !vec_aligned(p, x0) || !vec_aligned(p, x_out) ||
+      (reinterpret_cast<uintptr_t>(residuals) & 3))
+    return fail(SPFEL_EINVAL, "normal_solve: misaligned vector");
   if (iters < 0 || iters > 100000) return fail(SPFEL_EINVAL, "normal_solve: iters out of 0..100000");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool cplx = p->domain == SPFEL_COMPLEX;
@@ -481,6 +490,13 @@ int spfel_normal_lcurve(spfel_normal h, const void *x, const void *rhs, const vo
   int rc = check_lambdas(p, n, lambdas, lam, "normal_lcurve");
   if (rc != SPFEL_OK) return rc;
   if (!x || !rhs || !x0 || !rho_eta) return fail(SPFEL_EINVAL, "normal_lcurve: NULL pointer");
+  if (!vec_aligned(p, x) || !vec_aligned(p, rhs) || !vec_aligned(p, x0) ||
+      (reinterpret_cast<uintptr_t>(rho_eta) & 3) || (reinterpret_cast<uintptr_t>(corner) & 3))
+    return fail(SPFEL_EINVAL, "normal_lcurve: misaligned array");
+  if (n >= 3)
+    for (int s = 0; s < n; ++s)
+      if (!(lambdas[s] > 0.f))
+        return fail(SPFEL_EINVAL, "normal_lcurve: the corner needs lambdas > 0 (log spacing)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool cplx = p->domain == SPFEL_COMPLEX;
   const int64_t N3 = (int64_t)p->N * p->N * p->N, len = N3 * (cplx ? 2 : 1);

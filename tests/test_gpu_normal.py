@@ -208,6 +208,14 @@ def test_state_and_argument_errors():
     assert L.spfel_normal_apply(nm._h, v.data_ptr(), 3, lam, y.data_ptr(), None) == _lib.EINVAL
     assert L.spfel_normal_solve(nm._h, v.data_ptr(), v.data_ptr(), 1, lam, -1, y.data_ptr(),
                                 None, None) == _lib.EINVAL
+    # misaligned vector; an L-curve over lambdas that include 0
+    assert L.spfel_normal_apply(nm._h, v.data_ptr() + 2, 1, (ctypes.c_float * 1)(1.0),
+                                y.data_ptr(), None) == _lib.EINVAL
+    nm3 = spfel.Normal(7, device=DEV, max_systems=3)
+    nm3.set_psf(torch.zeros((13, 13, 13), dtype=torch.float32, device=DEV))
+    v3 = torch.zeros((3, 7, 7, 7), dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        nm3.lcurve(v3, v3[0], v3[0], [0.0, 1.0, 10.0], 0.0)
     torch.cuda.synchronize()
     nm.close()
     assert L.spfel_normal_set_psf(nm._h, v.data_ptr(), None) == _lib.ESTATE
