@@ -176,7 +176,7 @@ static void free_bins(Plan *p) {
 }
 
 // Scratch of the binned spread for detectors of P points: batches of up to
-// 2^26 points (and at most 65,536 images), key counts and offsets,
+// 2^27 points (and at most 65,536 images), key counts and offsets,
 // subproblem list.  Returns the bytes allocated, or 0 on failure (nothing
 // kept).
 static size_t alloc_bins(Plan *p, int64_t P) {

@@ -74,10 +74,11 @@ constexpr int kTile = 256;
 // Orientations per slicing launch (size of Plan::rot).
 constexpr int64_t kRotCap = 65536;
 // Binned spreading: brick side (cells), points per subproblem, points per
-// batch of images.
+// batch of images (2^27: 3.2 GB of staged points; every batch flushes each
+// occupied bin once, so larger batches flush less).
 constexpr int kBrick = 16;
 constexpr int kSubMax = 8192;
-constexpr int64_t kBinBatchPoints = (int64_t)1 << 26;
+constexpr int64_t kBinBatchPoints = (int64_t)1 << 27;
 size_t bin_keys(int nf, int w);
 size_t bin_max_subproblems(int nf, int w, int64_t cap);
 
