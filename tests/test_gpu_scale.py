@@ -2,8 +2,9 @@
 the type-1 adjoint (merging A*, section II-C Eq. (2)) of all 2,048 images of
 workload 2 (every image adds to the q ~ 0 cells, so the float32 atomic sums
 there are 2,048 deep) and of 256 images on the 129^3 / 258^3 grid of
-workload 5; and the weighted-loss gradient of the 65^3 complex model of
-workload 4 against the FP64 oracle and against central differences.  All
+workload 5; a merge of more images than one binning batch holds; and the
+weighted-loss gradient of the 65^3 complex model of workload 4 against the
+FP64 oracle and against central differences.  All
 through the registered-detector (tiled matrix-core spread) path; inputs are
 made without the library, expected values by the oracle only."""
 import numpy as np
