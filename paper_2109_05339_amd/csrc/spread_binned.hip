@@ -283,12 +283,15 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
   constexpr int kA = CPLX ? 2 : 1;
   // per wavefront and batch point: the brick-shifted rows y psi0 (re[, im])
   // and psi2 over the 16 brick cells of axes 0 and 2, and psi1 (its w
-  // values); row kPer is all zero (the pad of a partial group of four).
-  // The psi1 rows have an odd pitch (9), so the lanes writing their points'
-  // rows fall in distinct banks.
-  __shared__ __attribute__((aligned(16))) float rowA[4][kA][kPer + 1][kBrick];
-  __shared__ __attribute__((aligned(16))) float rowB[4][kPer + 1][kBrick];
-  __shared__ __attribute__((aligned(16))) float rowC[4][kPer + 1][9];
+  // values).  Rows past the batch's points are zero: the lanes past the
+  // batch write zero rows, and rows kPer .. kRows - 1 stay zero, so the
+  // matrix steps (which read up to seven rows past the last point) need no
+  // bound on their row index.  The psi1 rows have an odd pitch (9), so the
+  // lanes writing their points' rows fall in distinct banks.
+  constexpr int kRows = kPer + 7;
+  __shared__ __attribute__((aligned(16))) float rowA[4][kA][kRows][kBrick];
+  __shared__ __attribute__((aligned(16))) float rowB[4][kRows][kBrick];
+  __shared__ __attribute__((aligned(16))) float rowC[4][kRows][9];
   if ((int)blockIdx.x >= *nsub) return;   // block-uniform
   const int4 sp = sub[blockIdx.x];
   const int bin = sp.x, start = sp.y, end = sp.z;
@@ -301,13 +304,20 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
     accr[p] = floatx4{0.f, 0.f, 0.f, 0.f};
     if (CPLX) acci[CPLX ? p : 0] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
-  if (lane < kBrick) {
-    rowA[wave][0][kPer][lane] = 0.f;
-    if (CPLX) rowA[wave][kA - 1][kPer][lane] = 0.f;
-    rowB[wave][kPer][lane] = 0.f;
-    if (lane < 8) rowC[wave][kPer][lane] = 0.f;
+  for (int e = lane; e < (kRows - kPer) * kBrick; e += 64) {
+    const int row = kPer + e / kBrick, col = e % kBrick;
+    rowA[wave][0][row][col] = 0.f;
+    if (CPLX) rowA[wave][kA - 1][row][col] = 0.f;
+    rowB[wave][row][col] = 0.f;
+    if (col < 9) rowC[wave][row][col] = 0.f;
   }
   const int64_t key0 = (int64_t)bin * Bo;
+  // matrix-step reads: lane (r, kq) takes column r of row p0 + kq, a
+  // per-lane base plus a wavefront-uniform row offset
+  const float *const rdA = &rowA[wave][0][0][0] + kq * kBrick + r;
+  const float *const rdAi = &rowA[wave][kA - 1][0][0] + kq * kBrick + r;
+  const float *const rdB = &rowB[wave][0][0] + kq * kBrick + r;
+  const float *const rdC = &rowC[wave][0][0] + kq * 9;
 
   auto run = [&](auto vc) {
     constexpr int V = decltype(vc)::value;
@@ -317,14 +327,7 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
       // this batch's rows (the previous batch's reads were issued before
       // these writes, and a wavefront's LDS accesses complete in order)
       __builtin_amdgcn_wave_barrier();
-      if (lane < cnt) {
-        const float4 pv = pts[b0 + lane];
-        const uint2 ax = aux[b0 + lane];
-        const int o0 = ax.x & 15, o2 = (ax.x >> 8) & 15;
-        float w0[W], w1[W], w2[W];
-        es_weights<W>(pv.y, beta, w0);
-        es_weights<W>(pv.z, beta, w1);
-        es_weights<W>(pv.w, beta, w2);
+      {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -332,6 +335,18 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
           reinterpret_cast<float4 *>(rowB[wave][lane])[q] = z;
           if (CPLX) reinterpret_cast<float4 *>(rowA[wave][kA - 1][lane])[q] = z;
         }
+      }
+      if (lane >= cnt) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) rowC[wave][lane][a] = 0.f;
+      } else {
+        const float4 pv = pts[b0 + lane];
+        const uint2 ax = aux[b0 + lane];
+        const int o0 = ax.x & 15, o2 = (ax.x >> 8) & 15;
+        float w0[W], w1[W], w2[W];
+        es_weights<W>(pv.y, beta, w0);
+        es_weights<W>(pv.z, beta, w1);
+        es_weights<W>(pv.w, beta, w2);
         const float yi = __uint_as_float(ax.y);
 #pragma unroll
         for (int a = 0; a < W; ++a) {
@@ -348,13 +363,11 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
       // matrix instructions issue (the scheduling barriers keep them there).
       const int ucnt = __builtin_amdgcn_readfirstlane(cnt);
       auto fetch = [&](int p0, float &fa, float &fai, float &fb, float (&fc)[W]) {
-        const int p = p0 + kq;
-        const int pp = p < ucnt ? p : kPer;   // past the end: the zero row
-        fa = rowA[wave][0][pp][r];
-        fai = CPLX ? rowA[wave][kA - 1][pp][r] : 0.f;
-        fb = rowB[wave][pp][r];
+        fa = rdA[p0 * kBrick];
+        fai = CPLX ? rdAi[p0 * kBrick] : 0.f;
+        fb = rdB[p0 * kBrick];
 #pragma unroll
-        for (int d = 0; d < W; ++d) fc[d] = rowC[wave][pp][d];
+        for (int d = 0; d < W; ++d) fc[d] = rdC[p0 * 9 + d];
       };
       auto step = [&](float a, float ai, float bv, const float (&c)[W]) {
 #pragma unroll
