@@ -124,11 +124,19 @@ def test_merge_built_system_solves_like_the_dense_one(real):
                                   x0.astype(np.float64 if real else np.complex128), real)
         assert rel(xs[s], want) <= 5e-4, (s, lam, rel(xs[s], want))
         assert hist[s, -1] <= 1e-3 * hist[s, 0]
-    # REAL: the odd part of the solution is that of x0
+    # REAL: in exact arithmetic the odd part of the solution is that of x0
+    # (A^T D A acts on the even part only).  In float32 the operator's
+    # output C * even(x) is even only up to rounding, so every iteration
+    # feeds the odd part noise in proportion to the whole iterate: about
+    # sqrt(300 iterations) x 6 contractions x 14 terms x 2^-24 ~ 9e-5 of
+    # |x| as a random walk.  A wrong odd-part treatment (lambda applied to
+    # the even part only, or the kernel applied to x instead of even(x))
+    # moves it by O(|x|).
     if real:
         odd = 0.5 * (xs - xs[:, ::-1, ::-1, ::-1])
         odd0 = 0.5 * (x0 - x0[::-1, ::-1, ::-1])
-        assert rel(odd, np.broadcast_to(odd0, odd.shape)) <= 1e-5
+        for s in range(len(lams)):
+            assert np.linalg.norm(odd[s] - odd0) <= 1e-4 * np.linalg.norm(xs[s]), s
 
 
 @pytest.mark.parametrize("real", [True, False])
