@@ -7,6 +7,8 @@
 // exact squared distance of the rounded rows, and the per-row rounding
 // error norms computed here bound how far it can sit from the true one
 // (|sqrt(D) - sqrt(b)| <= e_m + f_n).
+#include <type_traits>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -50,6 +52,16 @@ hipError_t launch_column_mean(const float *x, int64_t rows, int64_t cols, int ro
 // scaled by `infl` (1 + gamma of its rounding chain) and the float32
 // subtraction's own rounding (at most 2^-24 |x - c| per element) is added
 // as 2^-23 |v|.
+// f32_to_bf16 written as a select instead of an early return (same
+// values, NaN stays NaN), so the streaming loop below carries no branch per
+// value and its loads stay grouped.
+__device__ inline uint16_t bf16_round(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t quiet = (u >> 16) | 0x40u;
+  return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
+}
+
 __global__ __launch_bounds__(256) void bf16_centred_kernel(
     const float *__restrict__ x, const float *__restrict__ c, int64_t cols,
     uint16_t *__restrict__ out, float *__restrict__ norm2, float *__restrict__ err, int vec,
@@ -61,7 +73,7 @@ __global__ __launch_bounds__(256) void bf16_centred_kernel(
   float a = 0.f, b = 0.f;
   auto one = [&](float v, float cc) -> uint16_t {
     const float d = v - cc;
-    const uint16_t h = f32_to_bf16(d);
+    const uint16_t h = bf16_round(d);
     const float r = bf16_to_f32(h);
     const float q = r - d;   // exact: r is d rounded to fewer bits
     a = fmaf(r, r, a);
@@ -73,13 +85,33 @@ __global__ __launch_bounds__(256) void bf16_centred_kernel(
     const float4 *x4 = reinterpret_cast<const float4 *>(xr);
     const float4 *c4 = reinterpret_cast<const float4 *>(c);
     uint2 *o2 = reinterpret_cast<uint2 *>(orow);
-    for (int64_t g = threadIdx.x; g < groups; g += 256) {
-      const float4 v = x4[g];
-      const float4 cc = c ? c4[g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    auto group = [&](int64_t g, float4 v, float4 cc) {
       const uint32_t h0 = one(v.x, cc.x), h1 = one(v.y, cc.y);
       const uint32_t h2 = one(v.z, cc.z), h3 = one(v.w, cc.w);
       o2[g] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
-    }
+    };
+    // four groups' loads in flight per thread; the sums still run over g
+    // in increasing order
+    auto walk = [&](auto has_c) {
+      constexpr bool C = decltype(has_c)::value;
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+      int64_t g = threadIdx.x;
+      for (; g + 3 * 256 < groups; g += 4 * 256) {
+        float4 v[4], cc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[u] = x4[g + u * 256];
+          cc[u] = C ? c4[g + u * 256] : z;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) group(g + u * 256, v[u], cc[u]);
+      }
+      for (; g < groups; g += 256) group(g, x4[g], C ? c4[g] : z);
+    };
+    if (c)
+      walk(std::true_type{});
+    else
+      walk(std::false_type{});
   } else {
     for (int64_t k = threadIdx.x; k < cols; k += 256) orow[k] = one(xr[k], c ? c[k] : 0.f);
   }
