@@ -151,7 +151,8 @@ __global__ __launch_bounds__(kTile) void bin_count_kernel(
 }
 
 // Pass 2: each point to its key's next slot.  aux = (packed origin,
-// imaginary value bits).
+// imaginary value bits); REAL stores the packed origin alone, as an array
+// of 32-bit words.
 template <int W, bool CPLX>
 __global__ __launch_bounds__(kTile) void bin_scatter_kernel(
     const double *__restrict__ rot, int64_t n0, const float *__restrict__ dets,
@@ -177,7 +178,11 @@ __global__ __launch_bounds__(kTile) void bin_scatter_kernel(
   if (slot >= 0) {
     const int pos = tbase[slot] + rank;
     pts[pos] = make_float4(b.yr, b.frac[0], b.frac[1], b.frac[2]);
-    aux[pos] = make_uint2((uint32_t)(b.o0 | (b.o1 << 4) | (b.o2 << 8)), __float_as_uint(b.yi));
+    const uint32_t packed = (uint32_t)(b.o0 | (b.o1 << 4) | (b.o2 << 8));
+    if (CPLX)
+      aux[pos] = make_uint2(packed, __float_as_uint(b.yi));
+    else
+      reinterpret_cast<uint32_t *>(aux)[pos] = packed;   // REAL: one word per point
   }
 }
 
@@ -341,7 +346,8 @@ __global__ __launch_bounds__(256) void spread_binned_kernel(
         for (int a = 0; a < W; ++a) rowC[wave][lane][a] = 0.f;
       } else {
         const float4 pv = pts[b0 + lane];
-        const uint2 ax = aux[b0 + lane];
+        const uint2 ax = CPLX ? aux[b0 + lane]
+                              : make_uint2(reinterpret_cast<const uint32_t *>(aux)[b0 + lane], 0u);
         const int o0 = ax.x & 15, o2 = (ax.x >> 8) & 15;
         float w0[W], w1[W], w2[W];
         es_weights<W>(pv.y, beta, w0);
