@@ -331,3 +331,21 @@ def test_full_size_launches_against_oracle_on_sampled_images(mode, M, N, P):
     np.testing.assert_array_equal(ib[cols], m1)
     np.testing.assert_array_equal(m1, host(pick)[cols])
     assert np.all(np.abs(db[cols] - ex[m1, c]) <= 2 * E[m1, c])
+
+
+def test_zero_sized_calls_leave_the_running_best_alone():
+    """No model images (M = 0): every image keeps its running best; no
+    images (n_img = 0): nothing to do.  Both return at once."""
+    g = np.random.default_rng(4)
+    D = gpu(g.random((5, 64)).astype(np.float32))
+    S0 = torch.zeros((0, 64), dtype=torch.float32, device=DEV)
+    bi = torch.full((5,), 7, dtype=torch.int32, device=DEV)
+    bd = torch.full((5,), 2.5, dtype=torch.float32, device=DEV)
+    spfel.match(S0, spfel.row_norm2(S0), D, spfel.row_norm2(D), bi, bd)
+    assert np.all(host(bi) == 7) and np.all(host(bd) == 2.5)
+    S = gpu(g.random((3, 64)).astype(np.float32))
+    D0 = torch.zeros((0, 64), dtype=torch.float32, device=DEV)
+    ei = torch.zeros((0,), dtype=torch.int32, device=DEV)
+    ed = torch.zeros((0,), dtype=torch.float32, device=DEV)
+    spfel.match(S, spfel.row_norm2(S), D0, spfel.row_norm2(D0), ei, ed)
+    torch.cuda.synchronize()

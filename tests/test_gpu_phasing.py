@@ -186,3 +186,14 @@ def test_hio_step_at_the_workload_size():
     want, we = ph.hio_step(f32(x), f32(A), sup, 0.9, meas, False)
     assert rel(host(r), want) <= 1e-5
     assert abs(float(host(err)[0]) - we) <= 1e-5 * we
+
+
+def test_zero_iterations_change_nothing():
+    N = 8
+    _, A, sup = blob_object(2, N)
+    x = (np.random.default_rng(9).random((N, N, N)) * sup).astype(np.float32)
+    p = spfel.Phase(N, device=DEV)
+    r = gpu(x)
+    err = p.iterate(r, gpu(A.astype(np.float32)), gpu(sup, torch.uint8), 0, errors=True)
+    assert tuple(err.shape) == (0,)
+    np.testing.assert_array_equal(host(r), x)
