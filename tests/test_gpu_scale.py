@@ -146,24 +146,32 @@ def test_workload4_gradient_against_central_differences():
     assert worst <= 1e-3
 
 
-def test_merge_across_binning_batches():
+@pytest.mark.parametrize("real", [True, False])
+def test_merge_across_binning_batches(real):
     """66,536 images of a 2 x 2 detector: more images than one binning batch
     takes (at most 65,536), so the merge runs two batches.  Against the
     oracle over all images, and equal to the sum of the merges of its two
     single-batch parts up to float32 rounding (a batch that read another
-    batch's images or values would break both)."""
+    batch's images or values would break both).  Both domains: they stage
+    their points in different layouts."""
     N, n = 13, 65536 + 1000
     det = detector(2)
     q = synth.quaternions(synth.config(1), "image_quats", n)
-    y = np.random.default_rng(31).random((n, len(det))).astype(np.float32)
-    plan = spfel.Plan(N, device=DEV)
+    g = np.random.default_rng(31)
+    if real:
+        y = g.random((n, len(det))).astype(np.float32)
+        yt = gpu(y)
+    else:
+        y = (g.random((n, len(det))) + 1j * g.standard_normal((n, len(det)))).astype(np.complex64)
+        yt = gpu(y, torch.complex64)
+    plan = spfel.Plan(N, domain=spfel.REAL if real else spfel.COMPLEX, device=DEV)
     plan.set_detector(gpu(det))
-    whole = host(plan.merge_adjoint(gpu(q), None, gpu(y)))
-    a = host(plan.merge_adjoint(gpu(q[:65536]), None, gpu(y[:65536])))
-    b = host(plan.merge_adjoint(gpu(q[65536:]), None, gpu(y[65536:])))
+    whole = host(plan.merge_adjoint(gpu(q), None, yt))
+    a = host(plan.merge_adjoint(gpu(q[:65536]), None, yt[:65536].contiguous()))
+    b = host(plan.merge_adjoint(gpu(q[65536:]), None, yt[65536:].contiguous()))
     assert rel(whole, a + b) <= TOL
     x = geometry.slice_points(f32(q), f32(det)).reshape(-1, 3)
-    ref = nufft.nufft1(y.astype(np.float64).ravel(), x, N, real=True)
+    ref = nufft.nufft1(y.astype(np.float64 if real else np.complex128).ravel(), x, N, real=real)
     err = rel(whole, ref)
-    print(f"merge of {n} images over two batches: rel L2 {err:.2e}")
+    print(f"merge of {n} images over two batches ({'real' if real else 'complex'}): rel L2 {err:.2e}")
     assert err <= TOL
