@@ -164,21 +164,26 @@ static bool aligned(const void *p, size_t a) {
 }
 
 static void free_bins(Plan *p) {
-  void *bufs[] = {p->bin_pts, p->bin_aux, p->bin_off, p->bin_cur, p->bin_part, p->bin_sub,
-                  p->bin_nsub};
+  void *bufs[] = {p->bin_pts[0], p->bin_pts[1], p->bin_aux[0], p->bin_aux[1], p->bin_off[0],
+                  p->bin_off[1], p->bin_cur, p->bin_part, p->bin_sub[0], p->bin_sub[1],
+                  p->bin_nsub[0], p->bin_nsub[1]};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
-  p->bin_pts = nullptr;
-  p->bin_aux = nullptr;
-  p->bin_off = p->bin_cur = p->bin_part = p->bin_nsub = nullptr;
-  p->bin_sub = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    p->bin_pts[k] = nullptr;
+    p->bin_aux[k] = nullptr;
+    p->bin_off[k] = p->bin_nsub[k] = nullptr;
+    p->bin_sub[k] = nullptr;
+  }
+  p->bin_cur = p->bin_part = nullptr;
   p->bin_cap = p->bin_batch = 0;
 }
 
 // Scratch of the binned spread for detectors of P points: batches of up to
 // 2^27 points (and at most 65,536 images), key counts and offsets,
-// subproblem list.  Returns the bytes allocated, or 0 on failure (nothing
-// kept).
+// subproblem list, the spread's inputs twice (binning and spreading of
+// consecutive batches overlap).  Returns the bytes allocated, or 0 on
+// failure (nothing kept).
 static size_t alloc_bins(Plan *p, int64_t P) {
   const int64_t per = std::max<int64_t>(1, std::min<int64_t>(kBinBatchPoints / P, 65536));
   const int64_t cap = per * P;
@@ -188,13 +193,18 @@ static size_t alloc_bins(Plan *p, int64_t P) {
   struct Req {
     void **ptr;
     size_t bytes;
-  } reqs[] = {{reinterpret_cast<void **>(&p->bin_pts), (size_t)cap * sizeof(float4)},
-              {reinterpret_cast<void **>(&p->bin_aux), (size_t)cap * sizeof(uint2)},
-              {reinterpret_cast<void **>(&p->bin_off), (keys + 1) * sizeof(int32_t)},
+  } reqs[] = {{reinterpret_cast<void **>(&p->bin_pts[0]), (size_t)cap * sizeof(float4)},
+              {reinterpret_cast<void **>(&p->bin_pts[1]), (size_t)cap * sizeof(float4)},
+              {reinterpret_cast<void **>(&p->bin_aux[0]), (size_t)cap * sizeof(uint2)},
+              {reinterpret_cast<void **>(&p->bin_aux[1]), (size_t)cap * sizeof(uint2)},
+              {reinterpret_cast<void **>(&p->bin_off[0]), (keys + 1) * sizeof(int32_t)},
+              {reinterpret_cast<void **>(&p->bin_off[1]), (keys + 1) * sizeof(int32_t)},
               {reinterpret_cast<void **>(&p->bin_cur), keys * sizeof(int32_t)},
               {reinterpret_cast<void **>(&p->bin_part), parts * sizeof(int32_t)},
-              {reinterpret_cast<void **>(&p->bin_sub), subs * sizeof(int4)},
-              {reinterpret_cast<void **>(&p->bin_nsub), 256}};
+              {reinterpret_cast<void **>(&p->bin_sub[0]), subs * sizeof(int4)},
+              {reinterpret_cast<void **>(&p->bin_sub[1]), subs * sizeof(int4)},
+              {reinterpret_cast<void **>(&p->bin_nsub[0]), 256},
+              {reinterpret_cast<void **>(&p->bin_nsub[1]), 256}};
   size_t total = 0;
   for (auto &r : reqs) {
     if (hipMalloc(r.ptr, r.bytes) != hipSuccess) {
@@ -216,10 +226,12 @@ static void free_plan(Plan *p) {
                   p->det_sorted, p->det_perm};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
-  hipEvent_t evs[] = {p->ev_start, p->ev_sliced[0], p->ev_sliced[1], p->ev_matched[0],
-                      p->ev_matched[1]};
+  hipEvent_t evs[] = {p->ev_start,     p->ev_sliced[0], p->ev_sliced[1], p->ev_matched[0],
+                      p->ev_matched[1], p->ev_bin_start, p->ev_binned[0], p->ev_binned[1],
+                      p->ev_spread[0],  p->ev_spread[1]};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
+  if (p->bin_stream) (void)hipStreamDestroy(p->bin_stream);
 }
 
 static bool m_offset_overflow(int64_t M) { return M > 0x7fffffffLL; }
@@ -309,7 +321,8 @@ int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
     p->bytes += r.bytes;
   }
   for (hipEvent_t *ev : {&p->ev_start, &p->ev_sliced[0], &p->ev_sliced[1], &p->ev_matched[0],
-                         &p->ev_matched[1]}) {
+                         &p->ev_matched[1], &p->ev_bin_start, &p->ev_binned[0], &p->ev_binned[1],
+                         &p->ev_spread[0], &p->ev_spread[1]}) {
     e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     if (e != hipSuccess) {
       *ev = nullptr;
@@ -317,6 +330,13 @@ int spfel_plan_create(spfel_plan *out, int n_model, int kernel_width,
       delete p;
       return hip_fail(e, "plan_create: hipEventCreate");
     }
+  }
+  e = hipStreamCreateWithFlags(&p->bin_stream, hipStreamNonBlocking);   // default priority
+  if (e != hipSuccess) {
+    p->bin_stream = nullptr;
+    free_plan(p);
+    delete p;
+    return hip_fail(e, "plan_create: hipStreamCreate");
   }
   // Transform tables in float64, rounded once to float32.  The phase index
   // k l is reduced modulo nf exactly before the trigonometric evaluation.

@@ -48,14 +48,16 @@ struct Plan {
   int64_t det_P = 0;
   // Binned spreading over the registered detector (allocated with it):
   // points of up to bin_batch images at a time, grouped by the fine-grid
-  // bin of their support origin and their axis-1 origin (the key).
-  float4 *bin_pts = nullptr;     // bin_cap: value (re), three kernel offsets
-  uint2 *bin_aux = nullptr;      // bin_cap: packed origin in the brick, value (im) bits
-  int32_t *bin_off = nullptr;    // keys + 1: counts, then exclusive offsets
-  int32_t *bin_cur = nullptr;    // keys: scatter cursors
-  int32_t *bin_part = nullptr;   // scan block totals
-  int4 *bin_sub = nullptr;       // subproblems (bin, first point, end)
-  int32_t *bin_nsub = nullptr;   // number of subproblems
+  // bin of their support origin and their axis-1 origin (the key).  Two
+  // sets of what the spread reads: batch b + 1 is binned into one while
+  // batch b spreads from the other.
+  float4 *bin_pts[2] = {nullptr, nullptr};    // bin_cap: value (re), three kernel offsets
+  uint2 *bin_aux[2] = {nullptr, nullptr};     // bin_cap: packed origin in the brick, value (im) bits
+  int32_t *bin_off[2] = {nullptr, nullptr};   // keys + 1: counts, then exclusive offsets
+  int32_t *bin_cur = nullptr;                 // keys: scatter cursors
+  int32_t *bin_part = nullptr;                // scan block totals
+  int4 *bin_sub[2] = {nullptr, nullptr};      // subproblems (bin, first point, end)
+  int32_t *bin_nsub[2] = {nullptr, nullptr};  // number of subproblems
   int64_t bin_cap = 0;           // points per batch
   int64_t bin_batch = 0;         // images per batch
   size_t bin_bytes = 0;
@@ -67,6 +69,13 @@ struct Plan {
   hipEvent_t ev_start = nullptr;
   hipEvent_t ev_sliced[2] = {nullptr, nullptr};
   hipEvent_t ev_matched[2] = {nullptr, nullptr};
+  // The binned merge's own stream (default priority) for the binning of
+  // the next batch, and its events: the caller's stream at entry, each
+  // buffer set binned, each buffer set spread.
+  hipStream_t bin_stream = nullptr;
+  hipEvent_t ev_bin_start = nullptr;
+  hipEvent_t ev_binned[2] = {nullptr, nullptr};
+  hipEvent_t ev_spread[2] = {nullptr, nullptr};
 };
 
 // Points per detector tile of the tiled slicing/spreading kernels.

@@ -490,32 +490,53 @@ static hipError_t spread_binned_wc(const Plan &pl, const float *quats, int64_t n
   const int64_t nkeys = nbins * Bo;
   const int tiles = (int)((P + kTile - 1) / kTile);
   const int64_t nparts = (nkeys + kScanBlock - 1) / kScanBlock;
-  for (int64_t n0 = 0; n0 < n_img; n0 += pl.bin_batch) {
+  // Batch b is binned on the plan's stream into buffer set b % 2 and
+  // spread on the caller's stream from it, so the binning of batch b + 1
+  // (memory and atomics) runs beside the spread of batch b (matrix cores).
+  // The plan's stream starts after the caller's work so far; every spread
+  // waits for its batch's binning, and the binning of batch b + 2 for the
+  // spread of batch b, which also orders all of it before the caller's
+  // later work.
+  hipStream_t bs = pl.bin_stream;
+  hipError_t e = hipEventRecord(pl.ev_bin_start, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(bs, pl.ev_bin_start, 0);
+  if (e != hipSuccess) return e;
+  int64_t b = 0;
+  for (int64_t n0 = 0; n0 < n_img; n0 += pl.bin_batch, ++b) {
+    const int k = (int)(b & 1);
     const int64_t nbat = std::min<int64_t>(pl.bin_batch, n_img - n0);
     const int64_t blocks = nbat * tiles;
-    hipError_t e = launch_rotations(quats + 4 * n0, nbat, (double)nf / (2.0 * M_PI), pl.rot, s);
-    if (e == hipSuccess) e = launch_fill_zero(pl.bin_off, (size_t)nkeys * 4, s);
+    if (b >= 2) {
+      e = hipStreamWaitEvent(bs, pl.ev_spread[k], 0);
+      if (e != hipSuccess) return e;
+    }
+    e = launch_rotations(quats + 4 * n0, nbat, (double)nf / (2.0 * M_PI), pl.rot, bs);
+    if (e == hipSuccess) e = launch_fill_zero(pl.bin_off[k], (size_t)nkeys * 4, bs);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bin_count_kernel<W, CPLX>), dim3((unsigned)blocks), dim3(kTile), 0, s,
-                       pl.rot, n0, pl.det_sorted, pl.det_perm, P, tiles, nf, nb, pl.bin_off);
-    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nparts), dim3(256), 0, s, pl.bin_off,
-                       nkeys, pl.bin_off, pl.bin_part);
-    hipLaunchKernelGGL(scan_part_kernel, dim3(1), dim3(256), 0, s, pl.bin_part, (int)nparts,
-                       pl.bin_off + nkeys);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, s,
-                       pl.bin_off, nkeys, pl.bin_part, pl.bin_cur);
-    e = launch_fill_zero(pl.bin_nsub, 4, s);
+    hipLaunchKernelGGL((bin_count_kernel<W, CPLX>), dim3((unsigned)blocks), dim3(kTile), 0, bs,
+                       pl.rot, n0, pl.det_sorted, pl.det_perm, P, tiles, nf, nb, pl.bin_off[k]);
+    hipLaunchKernelGGL(scan_local_kernel, dim3((unsigned)nparts), dim3(256), 0, bs,
+                       pl.bin_off[k], nkeys, pl.bin_off[k], pl.bin_part);
+    hipLaunchKernelGGL(scan_part_kernel, dim3(1), dim3(256), 0, bs, pl.bin_part, (int)nparts,
+                       pl.bin_off[k] + nkeys);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, bs,
+                       pl.bin_off[k], nkeys, pl.bin_part, pl.bin_cur);
+    e = launch_fill_zero(pl.bin_nsub[k], 4, bs);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(subproblem_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, s,
-                       pl.bin_off, (int)nbins, Bo, pl.bin_nsub, pl.bin_sub);
-    hipLaunchKernelGGL((bin_scatter_kernel<W, CPLX>), dim3((unsigned)blocks), dim3(kTile), 0, s,
+    hipLaunchKernelGGL(subproblem_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, bs,
+                       pl.bin_off[k], (int)nbins, Bo, pl.bin_nsub[k], pl.bin_sub[k]);
+    hipLaunchKernelGGL((bin_scatter_kernel<W, CPLX>), dim3((unsigned)blocks), dim3(kTile), 0, bs,
                        pl.rot, n0, pl.det_sorted, pl.det_perm, P, tiles, nf, nb, values, weights,
-                       pl.bin_cur, pl.bin_pts, pl.bin_aux);
+                       pl.bin_cur, pl.bin_pts[k], pl.bin_aux[k]);
+    e = hipEventRecord(pl.ev_binned[k], bs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, pl.ev_binned[k], 0);
+    if (e != hipSuccess) return e;
     const int64_t maxsub = (int64_t)bin_max_subproblems(nf, W, nbat * P);
     hipLaunchKernelGGL((spread_binned_kernel<W, CPLX>), dim3((unsigned)maxsub), dim3(256), 0, s,
-                       static_cast<float *>(pl.acc), nf, (float)pl.beta, nb, pl.bin_pts,
-                       pl.bin_aux, pl.bin_off, pl.bin_sub, pl.bin_nsub);
+                       static_cast<float *>(pl.acc), nf, (float)pl.beta, nb, pl.bin_pts[k],
+                       pl.bin_aux[k], pl.bin_off[k], pl.bin_sub[k], pl.bin_nsub[k]);
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(pl.ev_spread[k], s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
