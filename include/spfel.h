@@ -103,7 +103,8 @@ int spfel_plan_info(spfel_plan plan, int *n_fine, size_t *device_bytes);
  * same P) use it: each (orientation, patch) then stages its fine-grid brick
  * in LDS.  Outputs stay in the caller's pixel order.  This call copies the
  * points to the host (it synchronises `stream`) and allocates device memory;
- * it replaces any earlier registration. */
+ * it replaces any earlier registration, including the binned merge's
+ * staging (two sets of up to 2^27 points, 20 or 24 bytes each). */
 int spfel_set_detector(spfel_plan plan, const float *det_q, int64_t P,
                        void *stream);
 
@@ -265,7 +266,11 @@ int spfel_orient(spfel_plan plan, const float *quats, int64_t M,
  *                           deferred calls and writes out (out may be NULL
  *                           with DEFER).
  * Spreading uses float32 atomics, so the summation order (and the last bits
- * of the result) can vary between runs. */
+ * of the result) can vary between runs.  With the registered detector the
+ * points are binned in batches of up to 2^27 on a stream the plan owns
+ * (ordered after the work already on `stream`, and before the work queued
+ * on `stream` after this call) while the previous batch spreads on
+ * `stream`. */
 int spfel_merge_adjoint(spfel_plan plan, const float *quats, int64_t n_img,
                         const float *det_q, int64_t P, const void *values,
                         const float *weights, void *out, int flags,
